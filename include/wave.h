@@ -1,0 +1,193 @@
+/*
+ * wave.h -- C ABI of the time-tiled acoustic-wave sweep for MI355X (gfx950).
+ *
+ * What is computed.  The time-stepped finite-difference sweep for
+ *     m u_tt + damp u_t = lap u + q          (2D or 3D, space order 2..16)
+ * under time-tiling: several time steps fused per tile (the paper's
+ * contribution, implementation chapter, "Skewing" and "Time-tiling"), with
+ * the fused-step count T and the halo ("skew") depth per fused step as run-time
+ * parameters (parameterised tile sizes, Devito chapter, "Parameterisation").
+ * The skew must be at least the stencil radius so/2 (background chapter,
+ * "Validity of skewing factors"); smaller values are rejected.  Results of the
+ * time-tiled sweep are bitwise identical to the untiled sweep (evaluation
+ * chapter, "Functional correctness").
+ *
+ * The discretisation (the paper never prints it; see the library's design
+ * notes for every reading taken): leapfrog in time, order-`so` central
+ * differences in space with zero values outside the grid, centred damping
+ * damp = m * sigma with sigma = sigma_max * sum_a (d_a/nbl)^2 inside an
+ * absorbing layer nbl points wide at every face, sources injected and
+ * receivers sampled by multilinear interpolation:
+ *   u^{n+1} = [dt^2 (L u^n + sum_s w_s q_s^n) + 2 m u^n - (m - eta) u^{n-1}] / (m + eta),
+ *   eta = damp dt / 2,   d_r^n = sum_p w_{r,p} u^{n+1}_p.
+ * The adjoint is the same step run backwards in time; the gradient of
+ * J = 1/2 sum_n |d^n - d_obs^n|^2 with respect to m is accumulated by the
+ * imaging condition  g_p = -sum_j u^j_p ((1+st) mu^{j-1} - 2 mu^j + (1-st) mu^{j+1})_p,
+ * st = sigma dt / 2.
+ *
+ * Memory.  The library never allocates device memory.  The caller provides a
+ * persistent state buffer at wave_init (size from wave_state_bytes) and a
+ * scratch buffer per call (size from wave_scratch_bytes); both are device
+ * memory the caller owns and frees after wave_destroy.  All device pointers
+ * are plain FP32 arrays, row-major [n0][n1][n2] (2D: [n0][n1]) with the last
+ * axis of unit stride; axis 0 is the one streamed through registers.
+ * Coordinates are host FP64 arrays [count][ndim], metres from grid node 0.
+ *
+ * Streams and errors.  Every call is asynchronous on the stream given to
+ * wave_init (a hipStream_t passed as void*; NULL is the null stream) except
+ * where noted.  Every call returns a wave_status; nothing throws.  A kernel
+ * fault surfaces as WAVE_EHIP on a later call or synchronisation.  A context
+ * is not thread-safe; separate contexts are independent.
+ */
+#ifndef WAVETT_WAVE_H
+#define WAVETT_WAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WAVE_OK = 0,
+  WAVE_EINVAL = -1,       /* bad argument (sizes, pointers, order, shape) */
+  WAVE_ESKEW = -2,        /* skew < so/2: the fused tile would violate a dependence */
+  WAVE_ECFL = -3,         /* dt above the stability limit of the scheme */
+  WAVE_ENOMEM = -4,       /* state or scratch buffer smaller than required */
+  WAVE_EHIP = -5,         /* HIP runtime error (message in wave_last_error) */
+  WAVE_ESTATE = -6,       /* call sequence error (e.g. no checkpoints to reuse) */
+  WAVE_EUNSUPPORTED = -7  /* tile depth / tile shape not built for this order */
+} wave_status;
+
+/* Problem and schedule description. */
+typedef struct wave_desc {
+  int32_t ndim;          /* 2 or 3 */
+  int32_t space_order;   /* even, 2..16; stencil radius r = space_order/2 */
+  int64_t shape[3];      /* computational grid (absorbing layer included), n0 n1 [n2] */
+  double spacing[3];     /* metres per axis */
+  double dt;             /* seconds */
+  int32_t nbl;           /* absorbing-layer width in points; 0 = no damping */
+  double sigma_max;      /* damping maximum in 1/s (ignored if nbl == 0) */
+  int32_t time_tile;     /* T >= 1 fused steps per launch; 0 = autotune at init;
+                            -1 = untiled single-step sweep (the reference schedule) */
+  int32_t skew;          /* halo per fused step on the tiled axes; 0 = r; must be >= r */
+  int32_t tile_shape;    /* 0 = auto; 1 = 64x64 extended tile (1024 threads);
+                            2 = 32x64 extended tile (512 threads) (3D only) */
+  int32_t zchunks;       /* segments of axis 0 per launch; 0 = auto */
+} wave_desc;
+
+typedef struct wave_ctx wave_ctx;
+
+/* Bytes of the persistent device state for `d` (0 if d is invalid). */
+size_t wave_state_bytes(const wave_desc* d);
+
+/* Validate `d`, build the schedule and the per-axis damping tables, and derive
+ * b = dt^2/m from the model m_dev [N] (s^2/m^2, device, must stay > 0).  The
+ * CFL check uses max velocity 1/sqrt(min m): this call synchronises the
+ * stream once.  time_tile == 0 runs the autotuner here (synchronising, several
+ * trial sweeps).  state_dev must hold wave_state_bytes(d) bytes.
+ * Errors: WAVE_EINVAL, WAVE_ESKEW, WAVE_ECFL, WAVE_ENOMEM, WAVE_EUNSUPPORTED, WAVE_EHIP. */
+wave_status wave_init(const wave_desc* d, const float* m_dev, void* state_dev, size_t state_bytes,
+                      void* hip_stream, wave_ctx** out);
+
+/* Replace the model (same shape); re-checks the CFL limit (synchronises). */
+wave_status wave_set_model(wave_ctx* ctx, const float* m_dev);
+
+/* Change the schedule of an existing context: T >= 1 or -1 (untiled), skew
+ * (0 = r), tile_shape, zchunks as in wave_desc.  Host-only. */
+wave_status wave_set_schedule(wave_ctx* ctx, int32_t time_tile, int32_t skew, int32_t tile_shape,
+                              int32_t zchunks);
+
+/* Read back the schedule in use (after autotuning). Any pointer may be NULL. */
+wave_status wave_get_schedule(const wave_ctx* ctx, int32_t* time_tile, int32_t* skew, int32_t* tile_shape,
+                              int32_t* zchunks);
+
+/* Scratch bytes needed by wave_forward (adjoint = 0) or by wave_forward with
+ * checkpoints followed by wave_adjoint_grad (adjoint = 1) for nt steps with
+ * nsrc sources and nrec receivers; ckpt_every = K > 0 keeps a checkpoint of
+ * (u^{cK}, u^{cK-1}) for every segment. */
+size_t wave_scratch_bytes(const wave_ctx* ctx, int32_t nt, int32_t nsrc, int32_t nrec, int32_t ckpt_every,
+                          int32_t adjoint);
+
+/* Forward modelling, nt steps.
+ *   src_xyz  host [nsrc][ndim];  wavelet_dev device [nt][nsrc]  (q_s^n drives u^{n+1})
+ *   rec_xyz  host [nrec][ndim];  rec_dev device [nt][nrec] out (d^n samples u^{n+1}) or NULL
+ *   u_init_dev  device [2][N] = (u^0, u^{-1}) or NULL for zeros
+ *   u_final_dev device [2][N] out = (u^{nt}, u^{nt-1}) or NULL
+ *   ckpt_every  0: no checkpoints; K > 0: keep checkpoints in scratch so that a
+ *               following wave_adjoint_grad(..., reuse = 1) can skip the forward
+ *   scratch_dev / scratch_bytes  from wave_scratch_bytes(ctx, nt, nsrc, nrec, K, K > 0)
+ * Points outside the grid contribute nothing (their corners are dropped). */
+wave_status wave_forward(wave_ctx* ctx, int32_t nt,
+                         int32_t nsrc, const double* src_xyz, const float* wavelet_dev,
+                         int32_t nrec, const double* rec_xyz, float* rec_dev,
+                         const float* u_init_dev, float* u_final_dev,
+                         int32_t ckpt_every, void* scratch_dev, size_t scratch_bytes);
+
+/* Adjoint sweep and gradient, zero initial state.
+ *   resid_dev       device [nt][nrec]: dJ/dd (e.g. d - d_obs)
+ *   grad_m_dev      device [N] out: dJ/dm
+ *   grad_wavelet_dev device [nt][nsrc] out: dJ/dq, or NULL
+ *   ckpt_every      K >= 1 (segment length of the checkpointed recompute; K >= nt
+ *                   keeps the whole history)
+ *   reuse           1: use the checkpoints of the immediately preceding
+ *                   wave_forward on this context and scratch (same nt, K,
+ *                   geometry; else WAVE_ESTATE); 0: run that forward here.
+ * Forward segments are recomputed from checkpoints with the time-tiled
+ * kernel (storing their history), then swept backwards with the time-tiled
+ * adjoint kernel that accumulates the imaging condition. */
+wave_status wave_adjoint_grad(wave_ctx* ctx, int32_t nt,
+                              int32_t nsrc, const double* src_xyz, const float* wavelet_dev,
+                              int32_t nrec, const double* rec_xyz, const float* resid_dev,
+                              float* grad_m_dev, float* grad_wavelet_dev,
+                              int32_t ckpt_every, int32_t reuse, void* scratch_dev, size_t scratch_bytes);
+
+/* Many independent shots (own grids, orders, models, schedules) advanced
+ * together: every time window of every shot is one kernel launch per
+ * (radius, depth, shape) group, the whole sequence captured once into a HIP
+ * graph and replayed.  Forward only when grad_m is NULL; otherwise forward
+ * with checkpoints, then adjoint and gradient for every shot.  Arrays are
+ * per shot (length nshots); scratch[i] sized by wave_scratch_bytes.
+ * Stream: that of ctxs[0] (all contexts must share it). */
+wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
+                       const int32_t* nsrc, const double* const* src_xyz, const float* const* wavelet_dev,
+                       const int32_t* nrec, const double* const* rec_xyz, float* const* rec_dev,
+                       const float* const* resid_dev, float* const* grad_m_dev,
+                       int32_t ckpt_every, void* const* scratch_dev, const size_t* scratch_bytes);
+
+/* Autotune the schedule (T, skew, tile shape, zchunks) on this context's
+ * model by timing short trial sweeps; keeps the fastest (minimum of
+ * `repeats` trials per candidate).  Synchronises; needs scratch for
+ * `trial_steps` forward steps without sources.  max_T bounds the search. */
+wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
+                          void* scratch_dev, size_t scratch_bytes, double* best_seconds_per_step);
+
+/* Arithmetic-intensity estimators of the evaluation chapter ("Arithmetic
+ * intensity under time-tiling").  Host-only, no device access.
+ *   ai_space   AI of the space-tiled (untiled) sweep, flops per byte
+ *   t_t        time-tile size
+ *   ndim, D[], delta[], tile[]   extents, radii and tile sizes per spatial
+ *              dimension, ordered d_1 (outermost tile loop) .. d_n
+ *   omega      cache size in floats
+ * wave_ai_naive returns t_t * ai_space; wave_ai_tight divides that by
+ * 1 + |B| / prod D with |B| the union of re-loaded tile faces (face sizes
+ * F_i multiplied by t_t) -- the tighter bound of the same section. */
+double wave_ai_naive(double ai_space, int32_t t_t);
+double wave_ai_tight(double ai_space, int32_t t_t, int32_t ndim, const double* D, const double* delta,
+                     const double* tile, double omega);
+
+/* Flops per point-update of the sweep (adds + multiplies, FMA = 2) for order
+ * so in ndim dimensions, and compulsory HBM bytes per point-update of the
+ * schedule (T = -1 untiled; damping computed from indices). Host-only. */
+double wave_flops_per_point(int32_t ndim, int32_t space_order, int32_t damped);
+double wave_bytes_per_point(int32_t time_tile, int32_t mode);
+
+const char* wave_strerror(wave_status s);
+const char* wave_last_error(const wave_ctx* ctx);
+void wave_destroy(wave_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WAVETT_WAVE_H */

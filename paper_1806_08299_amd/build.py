@@ -1,0 +1,67 @@
+"""Build libwavett.so (the C-ABI library) for gfx950 with hipcc.
+
+Every translation unit is compiled in parallel into _build/, then linked into
+``paper_1806_08299_amd/libwavett.so``.  Flags that matter for results:
+
+* ``-ffp-contract=off``: no implicit fused multiply-adds, so the per-point
+  arithmetic is exactly the sequence written in wave_device.h in every kernel
+  (the time-tiled sweep must be bitwise identical to the untiled one);
+* ``-Xclang -target-feature -Xclang -packed-fp32-ops``: no packed FP32 ops;
+* no fast-math of any kind.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+ROOT = os.path.dirname(HERE)
+BUILD = os.path.join(ROOT, "_build")
+LIB = os.path.join(HERE, "libwavett.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH, "-ffp-contract=off",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I" + os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
+
+
+def sources():
+    srcs = [os.path.join(CSRC, "wave_api.cpp")]
+    srcs += [os.path.join(CSRC, "wave_r%d.hip" % r) for r in range(1, 9)]
+    return srcs
+
+
+def _compile(src: str) -> str:
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    cmd = [HIPCC, "-c", "-x", "hip", src, "-o", obj] + FLAGS
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
+    return obj
+
+
+def build(jobs: int = 0, verbose: bool = True) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    srcs = sources()
+    # largest units first
+    srcs.sort(key=lambda s: (0 if "wave_r1" in s or "wave_r2" in s else 1))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(_compile, srcs))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s\n%s" % (r.stdout, r.stderr))
+    os.replace(tmp, LIB)
+    if verbose:
+        print("built", LIB, file=sys.stderr)
+    return LIB
+
+
+if __name__ == "__main__":
+    build()

@@ -1,0 +1,1027 @@
+// wave_api.cpp -- host side of the C ABI declared in include/wave.h:
+// validation, schedule planning, source/receiver tables, the forward and
+// adjoint drivers (time windows, checkpoints, recompute), the autotuner and
+// the arithmetic-intensity estimators.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/wave.h"
+#include "wave_helpers.h"
+#include "wave_launch.h"
+
+using namespace wavett;
+
+// =========================================================== context
+
+struct wave_ctx {
+  wave_desc d;
+  int R = 0;
+  int dim = 3;
+  int64_t n0 = 1, n1 = 1, n2 = 1, N = 0;
+  Coefs C{};
+  // device state (carved from the caller's buffer)
+  float* b = nullptr;
+  float* w[4] = {nullptr, nullptr, nullptr, nullptr};
+  float* stz = nullptr;
+  float* sty = nullptr;
+  float* stx = nullptr;
+  hipStream_t stream = nullptr;
+  // schedule: T == -1 untiled kernel, T >= 1 tiled kernel
+  int T = -1, skew = 0, shape = 1, zchunks = 0;
+  int num_cu = 256;
+  size_t max_lds = 65536;
+  // checkpoints left by the last forward (for reuse by the adjoint)
+  struct {
+    bool valid = false;
+    int nt = 0, K = 0, nsrc = 0, nrec = 0;
+    const void* scratch = nullptr;
+    std::vector<double> src, rec;
+  } ck;
+  std::string err;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+wave_status fail(wave_ctx* c, wave_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                          \
+  do {                                                                              \
+    hipError_t _e = (expr);                                                         \
+    if (_e != hipSuccess)                                                           \
+      return fail(ctx, WAVE_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// Central second-derivative weights of order so, unit spacing (closed form).
+void fd_weights(int so, double* c) {
+  const int k = so / 2;
+  double s = 0.0;
+  for (int j = 1; j <= k; ++j) {
+    double r = 1.0;
+    for (int i = 1; i <= j; ++i) r *= double(k - i + 1) / double(k + i);
+    double cj = 2.0 * r / (double(j) * double(j));
+    if ((j & 1) == 0) cj = -cj;
+    c[j] = cj;
+    s += cj;
+  }
+  c[0] = -2.0 * s;
+}
+
+int64_t npts_of(const wave_desc* d) {
+  int64_t n = 1;
+  for (int a = 0; a < d->ndim; ++a) n *= d->shape[a];
+  return n;
+}
+
+wave_status check_desc(const wave_desc* d, std::string& msg) {
+  if (!d) { msg = "null descriptor"; return WAVE_EINVAL; }
+  if (d->ndim != 2 && d->ndim != 3) { msg = "ndim must be 2 or 3"; return WAVE_EINVAL; }
+  if (d->space_order < 2 || d->space_order > 16 || (d->space_order & 1)) {
+    msg = "space_order must be even in 2..16";
+    return WAVE_EINVAL;
+  }
+  for (int a = 0; a < d->ndim; ++a) {
+    if (d->shape[a] < 1 || d->shape[a] > (1 << 20)) { msg = "bad shape"; return WAVE_EINVAL; }
+    if (!(d->spacing[a] > 0.0) || !std::isfinite(d->spacing[a])) { msg = "bad spacing"; return WAVE_EINVAL; }
+  }
+  int64_t plane = d->ndim == 3 ? d->shape[1] * d->shape[2] : d->shape[1];
+  if (plane >= (int64_t(1) << 31)) { msg = "plane too large"; return WAVE_EINVAL; }
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt)) { msg = "bad dt"; return WAVE_EINVAL; }
+  if (d->nbl < 0) { msg = "nbl must be >= 0"; return WAVE_EINVAL; }
+  if (d->nbl > 0) {
+    for (int a = 0; a < d->ndim; ++a)
+      if (2 * (int64_t)d->nbl >= d->shape[a]) { msg = "absorbing layer wider than half the grid"; return WAVE_EINVAL; }
+    if (!(d->sigma_max >= 0.0) || !std::isfinite(d->sigma_max)) { msg = "bad sigma_max"; return WAVE_EINVAL; }
+  }
+  const int r = d->space_order / 2;
+  if (d->skew != 0 && d->skew < r) { msg = "skew below the stencil radius"; return WAVE_ESKEW; }
+  if (d->skew < 0) { msg = "bad skew"; return WAVE_EINVAL; }
+  if (d->time_tile < -1 || d->time_tile > 8) { msg = "time_tile must be -1, 0 or 1..8"; return WAVE_EINVAL; }
+  if (d->tile_shape < 0 || d->tile_shape > 2) { msg = "tile_shape must be 0, 1 or 2"; return WAVE_EINVAL; }
+  if (d->zchunks < 0) { msg = "zchunks must be >= 0"; return WAVE_EINVAL; }
+  return WAVE_OK;
+}
+
+// Von Neumann limit: stable iff c_max dt sqrt(sum_a rho / h_a^2) <= 2 with
+// rho = -(c_0 + 2 sum_j (-1)^j c_j), the symbol's magnitude at Nyquist.
+double cfl_number(const wave_desc* d, double c_max) {
+  double c[9];
+  fd_weights(d->space_order, c);
+  double rho = -c[0];
+  for (int j = 1; j <= d->space_order / 2; ++j) rho -= 2.0 * c[j] * ((j & 1) ? -1.0 : 1.0);
+  double s = 0.0;
+  for (int a = 0; a < d->ndim; ++a) s += rho / (d->spacing[a] * d->spacing[a]);
+  return c_max * d->dt * std::sqrt(s) / 2.0;
+}
+
+// ----------------------------------------------------------- point tables
+
+// Unique grid points touched by a set of positions (multilinear corners),
+// sorted by linear index = (z, y, x); plus the forward map position -> corners
+// and the inverse map point -> (position, weight) in a fixed order.
+struct PointTable {
+  int npos = 0, npts = 0;
+  std::vector<int32_t> zptr, y, x;          // per unique point; zptr over axis 0
+  std::vector<int32_t> pos_ptr, corner_pt;  // position -> corners
+  std::vector<float> corner_w;
+  std::vector<int32_t> pt_ptr, pt_src;      // point -> contributions
+  std::vector<float> pt_w;
+};
+
+void build_points(const wave_ctx* c, int npos, const double* xyz, PointTable& P) {
+  const int nd = c->dim;
+  const int64_t n[3] = {c->n0, nd == 3 ? c->n1 : c->n2, c->n2};
+  struct Corner { int64_t lin; int pos; float w; };
+  std::vector<Corner> corners;
+  P.npos = npos;
+  P.pos_ptr.assign(npos + 1, 0);
+  std::vector<std::vector<std::pair<int64_t, float>>> per(npos);
+  for (int p = 0; p < npos; ++p) {
+    int64_t i0[3] = {0, 0, 0};
+    double f[3] = {0, 0, 0};
+    for (int a = 0; a < nd; ++a) {
+      const double xi = xyz[(size_t)p * nd + a] / c->d.spacing[a];
+      const double fl = std::floor(xi);
+      i0[a] = (int64_t)fl;
+      f[a] = xi - fl;
+    }
+    for (int bits = 0; bits < (1 << nd); ++bits) {
+      double w = 1.0;
+      int64_t lin = 0;
+      bool inside = true;
+      for (int a = 0; a < nd; ++a) {
+        const int bit = (bits >> (nd - 1 - a)) & 1;
+        const int64_t ia = i0[a] + bit;
+        if (ia < 0 || ia >= n[a]) inside = false;
+        w *= bit ? f[a] : 1.0 - f[a];
+        lin = lin * n[a] + ia;
+      }
+      if (!inside || w == 0.0) continue;
+      per[p].push_back({lin, (float)w});
+    }
+  }
+  std::vector<int64_t> lins;
+  for (auto& v : per)
+    for (auto& e : v) lins.push_back(e.first);
+  std::sort(lins.begin(), lins.end());
+  lins.erase(std::unique(lins.begin(), lins.end()), lins.end());
+  P.npts = (int)lins.size();
+  const int64_t plane = (nd == 3) ? c->n1 * c->n2 : c->n2;
+  P.zptr.assign(c->n0 + 1, 0);
+  P.y.resize(P.npts);
+  P.x.resize(P.npts);
+  for (int u = 0; u < P.npts; ++u) {
+    const int64_t z = lins[u] / plane, rem = lins[u] % plane;
+    P.y[u] = (nd == 3) ? (int32_t)(rem / c->n2) : 0;
+    P.x[u] = (int32_t)(rem % c->n2);
+    P.zptr[z + 1]++;
+  }
+  for (int64_t z = 0; z < c->n0; ++z) P.zptr[z + 1] += P.zptr[z];
+  auto find = [&](int64_t lin) { return (int32_t)(std::lower_bound(lins.begin(), lins.end(), lin) - lins.begin()); };
+  P.corner_pt.clear();
+  P.corner_w.clear();
+  std::vector<std::vector<std::pair<int32_t, float>>> inv(P.npts);
+  for (int p = 0; p < npos; ++p) {
+    P.pos_ptr[p] = (int32_t)P.corner_pt.size();
+    for (auto& e : per[p]) {
+      const int32_t u = find(e.first);
+      P.corner_pt.push_back(u);
+      P.corner_w.push_back(e.second);
+      inv[u].push_back({p, e.second});
+    }
+  }
+  P.pos_ptr[npos] = (int32_t)P.corner_pt.size();
+  P.pt_ptr.assign(P.npts + 1, 0);
+  P.pt_src.clear();
+  P.pt_w.clear();
+  for (int u = 0; u < P.npts; ++u) {
+    P.pt_ptr[u] = (int32_t)P.pt_src.size();
+    for (auto& e : inv[u]) {
+      P.pt_src.push_back(e.first);
+      P.pt_w.push_back(e.second);
+    }
+  }
+  P.pt_ptr[P.npts] = (int32_t)P.pt_src.size();
+}
+
+// Device image of a PointTable (int32/float arrays back to back).
+struct DevPoints {
+  PointSet set{};
+  const int32_t* pos_ptr = nullptr;
+  const int32_t* corner_pt = nullptr;
+  const float* corner_w = nullptr;
+  const int32_t* pt_ptr = nullptr;
+  const int32_t* pt_src = nullptr;
+  const float* pt_w = nullptr;
+  int npos = 0;
+};
+
+size_t table_bytes_bound(int64_t n0, int npos, int nd) {
+  const size_t maxc = (size_t)npos << nd;
+  return align_up(sizeof(int32_t) * ((size_t)n0 + 1 + 2 * maxc + (npos + 1) + 2 * maxc + (maxc + 1) + 2 * maxc) + 64);
+}
+
+// Carves a scratch region and copies the tables into it (async on stream).
+wave_status upload_points(wave_ctx* c, const PointTable& P, char*& cursor, DevPoints& D, std::vector<char>& host) {
+  host.clear();
+  auto put = [&](const void* p, size_t bytes) {
+    size_t off = host.size();
+    host.resize(off + bytes);
+    if (bytes) std::memcpy(host.data() + off, p, bytes);
+    return off;
+  };
+  const size_t o_z = put(P.zptr.data(), P.zptr.size() * 4);
+  const size_t o_y = put(P.y.data(), P.y.size() * 4);
+  const size_t o_x = put(P.x.data(), P.x.size() * 4);
+  const size_t o_pp = put(P.pos_ptr.data(), P.pos_ptr.size() * 4);
+  const size_t o_cp = put(P.corner_pt.data(), P.corner_pt.size() * 4);
+  const size_t o_cw = put(P.corner_w.data(), P.corner_w.size() * 4);
+  const size_t o_tp = put(P.pt_ptr.data(), P.pt_ptr.size() * 4);
+  const size_t o_ts = put(P.pt_src.data(), P.pt_src.size() * 4);
+  const size_t o_tw = put(P.pt_w.data(), P.pt_w.size() * 4);
+  char* base = cursor;
+  if (!host.empty()) HIP_TRY(c, hipMemcpyAsync(base, host.data(), host.size(), hipMemcpyHostToDevice, c->stream));
+  cursor += align_up(host.size());
+  D.set.zptr = (const int32_t*)(base + o_z);
+  D.set.y = (const int32_t*)(base + o_y);
+  D.set.x = (const int32_t*)(base + o_x);
+  D.set.npts = P.npts;
+  D.pos_ptr = (const int32_t*)(base + o_pp);
+  D.corner_pt = (const int32_t*)(base + o_cp);
+  D.corner_w = (const float*)(base + o_cw);
+  D.pt_ptr = (const int32_t*)(base + o_tp);
+  D.pt_src = (const int32_t*)(base + o_ts);
+  D.pt_w = (const float*)(base + o_tw);
+  D.npos = P.npos;
+  return WAVE_OK;
+}
+
+dim3 grid1d(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536)));
+}
+
+wave_status fill(wave_ctx* c, float* p, int64_t n, float v) {
+  if (n <= 0) return WAVE_OK;
+  hipLaunchKernelGGL(k_fill, grid1d(n), dim3(256), 0, c->stream, p, n, v);
+  HIP_TRY(c, hipGetLastError());
+  return WAVE_OK;
+}
+
+wave_status copy(wave_ctx* c, const float* s, float* d, int64_t n) {
+  if (n <= 0) return WAVE_OK;
+  hipLaunchKernelGGL(k_copy, grid1d(n), dim3(256), 0, c->stream, s, d, n);
+  HIP_TRY(c, hipGetLastError());
+  return WAVE_OK;
+}
+
+// ----------------------------------------------------------- schedule
+
+struct Plan {
+  int kind, T, shape;
+  int tiles_x, tiles_y, zchunk, zc;
+  size_t lds;
+  int core_y, core_x;
+};
+
+int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T) {
+  const int64_t target = (kind == KIND_UNTILED) ? 8LL * c->num_cu : 2LL * c->num_cu;
+  int64_t zc = (target + base_blocks - 1) / base_blocks;
+  const int64_t min_len = (kind == KIND_UNTILED) ? 16 : std::max<int64_t>(16, 4LL * T * c->R);
+  zc = std::min<int64_t>(zc, std::max<int64_t>(1, c->n0 / min_len));
+  return (int)std::max<int64_t>(1, zc);
+}
+
+wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p) {
+  p.kind = kind;
+  p.T = T;
+  p.shape = (c->dim == 3) ? c->shape : 0;
+  BlockShape bs = block_shape(kind, c->dim, p.shape);
+  if (kind == KIND_UNTILED) {
+    p.core_y = bs.ey;
+    p.core_x = bs.ex;
+    p.lds = 0;
+  } else {
+    if (T < 1 || T > tiled_tmax(c->R, c->dim, p.shape))
+      return fail(c, WAVE_EUNSUPPORTED, "time-tile depth not built for this order and tile shape");
+    const int H = c->skew * T;
+    p.core_x = bs.ex - 2 * H;
+    p.core_y = (c->dim == 3) ? bs.ey - 2 * H : 1;
+    if (p.core_x < 1 || p.core_y < 1)
+      return fail(c, WAVE_EUNSUPPORTED, "halo (skew * T) leaves no core in the extended tile");
+    const int ry = (c->dim == 3) ? c->R : 0;
+    p.lds = (size_t)T * (bs.ey + 2 * ry) * (bs.ex + 2 * c->R) * sizeof(float);
+    if (p.lds > c->max_lds) return fail(c, WAVE_EUNSUPPORTED, "tile needs more LDS than a workgroup can hold");
+  }
+  const int64_t ny = (c->dim == 3) ? c->n1 : 1;
+  p.tiles_x = (int)((c->n2 + p.core_x - 1) / p.core_x);
+  p.tiles_y = (int)((ny + p.core_y - 1) / p.core_y);
+  const int64_t base = (int64_t)p.tiles_x * p.tiles_y;
+  int zc = c->zchunks > 0 ? c->zchunks : auto_zchunks(c, base, kind, T);
+  zc = (int)std::min<int64_t>(zc, c->n0);
+  p.zchunk = (int)((c->n0 + zc - 1) / zc);
+  p.zc = (int)((c->n0 + p.zchunk - 1) / p.zchunk);
+  return WAVE_OK;
+}
+
+SweepArgs base_args(const wave_ctx* c) {
+  SweepArgs A{};
+  A.C = c->C;
+  A.n0 = (int32_t)c->n0;
+  A.n1 = (int32_t)((c->dim == 3) ? c->n1 : 1);
+  A.n2 = (int32_t)c->n2;
+  A.s1 = c->n2;
+  A.s0 = (int64_t)A.n1 * c->n2;
+  A.b = c->b;
+  A.has_damp = (c->d.nbl > 0 && c->d.sigma_max > 0.0) ? 1 : 0;
+  A.stz = c->stz;
+  A.sty = (c->dim == 3) ? c->sty : nullptr;
+  A.stx = c->stx;
+  A.skew = c->skew;
+  A.dir = 1;
+  return A;
+}
+
+// One launch advancing `T` steps (T = 1 for the untiled kernel).
+wave_status launch_window(wave_ctx* c, const Plan& p, SweepArgs A) {
+  A.core_y = p.core_y;
+  A.core_x = p.core_x;
+  A.tiles_x = p.tiles_x;
+  A.zchunk = p.zchunk;
+  dim3 grid((unsigned)((int64_t)p.tiles_x * p.tiles_y), (unsigned)p.zc);
+  int mode = MODE_FWD;
+  if (A.grad) mode = MODE_ADJ;
+  else if (A.hist) mode = MODE_HIST;
+  hipError_t e = launch_sweep(c->R, p.kind, p.T, c->dim, mode, p.shape, A, grid, p.lds, c->stream);
+  if (e != hipSuccess) return fail(c, WAVE_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
+  return WAVE_OK;
+}
+
+// Rolling set of four wavefield buffers: (cur, prev) plus two free ones.
+struct Waves {
+  float* buf[4];
+  int cur = 0, prev = 1;
+  float* C() const { return buf[cur]; }
+  float* P() const { return buf[prev]; }
+};
+
+// Advance `steps` steps starting at step index `step0` (direction dir), using
+// windows of the context's depth.  Stops windows at multiples of `cut`
+// (relative to cut_origin) when cut > 0.
+struct Window {
+  const DevPoints* inj;
+  const float* inj_table;
+  const DevPoints* smp;
+  float* smp_out;
+  float* hist;
+  int hist_base;
+  float* grad;
+};
+
+wave_status run_steps(wave_ctx* c, Waves& W, int step0, int steps, int dir, const Window& win) {
+  int done = 0;
+  const bool untiled = (c->T < 0);
+  while (done < steps) {
+    int T = untiled ? 1 : std::min(c->T, steps - done);
+    Plan p;
+    wave_status s = make_plan(c, untiled ? KIND_UNTILED : KIND_TILED, T, p);
+    if (s != WAVE_OK) return s;
+    SweepArgs A = base_args(c);
+    A.cur = W.C();
+    A.prev = W.P();
+    if (win.inj) {
+      A.inj = win.inj->set;
+      A.inj_table = win.inj_table;
+    }
+    if (win.smp) {
+      A.smp = win.smp->set;
+      A.smp_out = win.smp_out;
+    }
+    A.hist = win.hist;
+    A.hist_base = win.hist_base;
+    A.grad = win.grad;
+    A.step0 = step0 + dir * done;
+    A.dir = dir;
+    int nc, np;
+    if (untiled || T == 1) {
+      A.outA = W.P();   // in place over the oldest level
+      A.outB = nullptr;
+      nc = W.prev;
+      np = W.cur;
+    } else {
+      int f[2], k = 0;
+      for (int i = 0; i < 4; ++i)
+        if (i != W.cur && i != W.prev) f[k++] = i;
+      A.outA = W.buf[f[0]];
+      A.outB = W.buf[f[1]];
+      nc = f[0];
+      np = f[1];
+    }
+    s = launch_window(c, p, A);
+    if (s != WAVE_OK) return s;
+    W.cur = nc;
+    W.prev = np;
+    done += T;
+  }
+  return WAVE_OK;
+}
+
+// ----------------------------------------------------------- scratch layout
+
+struct Layout {
+  size_t tab_src = 0, tab_rec = 0;   // point tables
+  size_t inj = 0;                    // forcing table [nt][npts_src]
+  size_t smp = 0;                    // sample buffer [nt][npts_rec]
+  size_t ckpt = 0;                   // [nseg][2][N]
+  size_t adj_inj = 0, adj_smp = 0;   // adjoint forcing [nt][npts_rec], samples [nt][npts_src]
+  size_t hist = 0;                   // [K][N]
+  size_t adj_w = 0;                  // [4][N]
+  size_t total = 0;
+  int nseg = 0;
+};
+
+Layout layout(const wave_ctx* c, int nt, int nsrc, int nrec, int K, int adjoint) {
+  Layout L;
+  const int nd = c->dim;
+  size_t o = 0;
+  L.tab_src = o; o += table_bytes_bound(c->n0, nsrc, nd);
+  L.tab_rec = o; o += table_bytes_bound(c->n0, nrec, nd);
+  L.inj = o; o += align_up(sizeof(float) * (size_t)nt * ((size_t)nsrc << nd));
+  L.smp = o; o += align_up(sizeof(float) * (size_t)nt * ((size_t)nrec << nd));
+  if (K > 0) {
+    L.nseg = (nt + K - 1) / K;
+    L.ckpt = o; o += align_up(sizeof(float) * (size_t)L.nseg * 2 * c->N);
+  }
+  if (adjoint) {
+    const int Kh = std::min(std::max(K, 1), std::max(nt, 1));
+    L.adj_inj = o; o += align_up(sizeof(float) * (size_t)nt * ((size_t)nrec << nd));
+    L.adj_smp = o; o += align_up(sizeof(float) * (size_t)nt * ((size_t)nsrc << nd));
+    L.hist = o; o += align_up(sizeof(float) * (size_t)Kh * c->N);
+    L.adj_w = o; o += align_up(sizeof(float) * 4 * (size_t)c->N);
+  }
+  L.total = o;
+  return L;
+}
+
+wave_status validate_coords(wave_ctx* c, int n, const double* xyz) {
+  if (n < 0) return fail(c, WAVE_EINVAL, "negative point count");
+  if (n > 0 && !xyz) return fail(c, WAVE_EINVAL, "null coordinates");
+  for (int64_t i = 0; i < (int64_t)n * c->dim; ++i)
+    if (!std::isfinite(xyz[i])) return fail(c, WAVE_EINVAL, "non-finite coordinate");
+  return WAVE_OK;
+}
+
+// Forward core shared by wave_forward and the adjoint's own forward.
+wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const float* wav, int nrec,
+                         const double* rec, float* rec_out, const float* u_init, float* u_final, int K,
+                         char* scratch, const Layout& L) {
+  PointTable PS, PR;
+  build_points(c, nsrc, src, PS);
+  build_points(c, rec_out ? nrec : 0, rec, PR);
+  DevPoints DS, DR;
+  std::vector<char> h1, h2;
+  char* cur = scratch + L.tab_src;
+  wave_status s = upload_points(c, PS, cur, DS, h1);
+  if (s) return s;
+  cur = scratch + L.tab_rec;
+  s = upload_points(c, PR, cur, DR, h2);
+  if (s) return s;
+  float* table = (float*)(scratch + L.inj);
+  float* samp = (float*)(scratch + L.smp);
+  if (PS.npts > 0) {
+    hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * PS.npts), dim3(256), 0, c->stream, wav, nsrc, nt,
+                       DS.pt_ptr, DS.pt_src, DS.pt_w, PS.npts, 1.0f, table);
+    HIP_TRY(c, hipGetLastError());
+  }
+  if (PR.npts > 0) {
+    s = fill(c, samp, (int64_t)nt * PR.npts, 0.0f);
+    if (s) return s;
+  }
+  Waves W;
+  for (int i = 0; i < 4; ++i) W.buf[i] = c->w[i];
+  if (u_init) {
+    if ((s = copy(c, u_init, W.C(), c->N))) return s;
+    if ((s = copy(c, u_init + c->N, W.P(), c->N))) return s;
+  } else {
+    if ((s = fill(c, W.C(), c->N, 0.0f))) return s;
+    if ((s = fill(c, W.P(), c->N, 0.0f))) return s;
+  }
+  float* ck = K > 0 ? (float*)(scratch + L.ckpt) : nullptr;
+  Window win{&DS, table, PR.npts > 0 ? &DR : nullptr, samp, nullptr, 0, nullptr};
+  int n = 0;
+  while (n < nt) {
+    if (ck && n % K == 0) {
+      const int seg = n / K;
+      if ((s = copy(c, W.C(), ck + (size_t)seg * 2 * c->N, c->N))) return s;
+      if ((s = copy(c, W.P(), ck + (size_t)seg * 2 * c->N + c->N, c->N))) return s;
+    }
+    const int upto = ck ? std::min(nt, (n / K + 1) * K) : nt;
+    if ((s = run_steps(c, W, n, upto - n, 1, win))) return s;
+    n = upto;
+  }
+  if (rec_out && nrec > 0) {
+    if (PR.npts > 0) {
+      hipLaunchKernelGGL(k_reduce_samples, grid1d((int64_t)nt * nrec), dim3(256), 0, c->stream, samp, PR.npts, nt,
+                         DR.pos_ptr, DR.corner_pt, DR.corner_w, nrec, 1.0f, rec_out);
+      HIP_TRY(c, hipGetLastError());
+    } else {
+      if ((s = fill(c, rec_out, (int64_t)nt * nrec, 0.0f))) return s;
+    }
+  }
+  if (u_final) {
+    if ((s = copy(c, W.C(), u_final, c->N))) return s;
+    if ((s = copy(c, W.P(), u_final + c->N, c->N))) return s;
+  }
+  return WAVE_OK;
+}
+
+}  // namespace
+
+// =========================================================== dispatch tables
+
+namespace wavett {
+
+BlockShape block_shape(int kind, int dim, int shape) {
+  if (dim == 2) return {4, 4, 1, 1024};
+  if (kind == KIND_UNTILED) return {4, 4, 16, 64};
+  if (shape == 2) return {8, 4, 32, 64};
+  return {16, 4, 64, 64};
+}
+
+int tiled_tmax(int R, int dim, int shape) {
+  if (R < 1 || R > 8) return 0;
+  if (dim == 2) return kTmax2D[R];
+  return shape == 2 ? kTmax3D_S2[R] : kTmax3D_S1[R];
+}
+
+hipError_t launch_sweep(int R, int kind, int T, int dim, int mode, int shape, const SweepArgs& A, dim3 grid,
+                        size_t lds, hipStream_t s) {
+  switch (R) {
+    case 1: return launch_sweep_r1(kind, T, dim, mode, shape, A, grid, lds, s);
+    case 2: return launch_sweep_r2(kind, T, dim, mode, shape, A, grid, lds, s);
+    case 3: return launch_sweep_r3(kind, T, dim, mode, shape, A, grid, lds, s);
+    case 4: return launch_sweep_r4(kind, T, dim, mode, shape, A, grid, lds, s);
+    case 5: return launch_sweep_r5(kind, T, dim, mode, shape, A, grid, lds, s);
+    case 6: return launch_sweep_r6(kind, T, dim, mode, shape, A, grid, lds, s);
+    case 7: return launch_sweep_r7(kind, T, dim, mode, shape, A, grid, lds, s);
+    case 8: return launch_sweep_r8(kind, T, dim, mode, shape, A, grid, lds, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace wavett
+
+// =========================================================== C ABI
+
+extern "C" {
+
+const char* wave_strerror(wave_status s) {
+  switch (s) {
+    case WAVE_OK: return "ok";
+    case WAVE_EINVAL: return "invalid argument";
+    case WAVE_ESKEW: return "skew below the stencil radius (illegal time tile)";
+    case WAVE_ECFL: return "time step above the stability limit";
+    case WAVE_ENOMEM: return "buffer too small";
+    case WAVE_EHIP: return "HIP runtime error";
+    case WAVE_ESTATE: return "invalid call sequence";
+    case WAVE_EUNSUPPORTED: return "schedule not available for this order/shape";
+  }
+  return "unknown status";
+}
+
+const char* wave_last_error(const wave_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+size_t wave_state_bytes(const wave_desc* d) {
+  std::string msg;
+  wave_status s = check_desc(d, msg);
+  if (s != WAVE_OK && s != WAVE_ESKEW) return 0;
+  const int64_t N = npts_of(d);
+  size_t o = align_up(sizeof(float) * N);          // b
+  o += 4 * align_up(sizeof(float) * N);             // wavefields
+  for (int a = 0; a < d->ndim; ++a) o += align_up(sizeof(float) * d->shape[a]);
+  return o;
+}
+
+static wave_status apply_schedule(wave_ctx* c, int T, int skew, int shape, int zchunks) {
+  if (skew != 0 && skew < c->R) return fail(c, WAVE_ESKEW, "skew below the stencil radius");
+  if (skew < 0 || zchunks < 0 || shape < 0 || shape > 2 || T < -1 || T > 8 || T == 0)
+    return fail(c, WAVE_EINVAL, "bad schedule");
+  c->T = T;
+  c->skew = skew ? skew : c->R;
+  c->shape = (c->dim == 3) ? (shape ? shape : 1) : 0;
+  c->zchunks = zchunks;
+  if (T >= 1) {
+    Plan p;
+    wave_status s = make_plan(c, KIND_TILED, T, p);
+    if (s != WAVE_OK) return s;
+  }
+  return WAVE_OK;
+}
+
+wave_status wave_set_schedule(wave_ctx* c, int32_t T, int32_t skew, int32_t shape, int32_t zchunks) {
+  if (!c) return WAVE_EINVAL;
+  const int oT = c->T, os = c->skew, osh = c->shape, oz = c->zchunks;
+  wave_status s = apply_schedule(c, T, skew, shape, zchunks);
+  if (s != WAVE_OK) {
+    c->T = oT; c->skew = os; c->shape = osh; c->zchunks = oz;
+  }
+  return s;
+}
+
+wave_status wave_get_schedule(const wave_ctx* c, int32_t* T, int32_t* skew, int32_t* shape, int32_t* zchunks) {
+  if (!c) return WAVE_EINVAL;
+  if (T) *T = c->T;
+  if (skew) *skew = c->skew;
+  if (shape) *shape = c->shape;
+  if (zchunks) *zchunks = c->zchunks;
+  return WAVE_OK;
+}
+
+// min(m) on the device, one float back to the host.
+__global__ void k_min_reduce(const float* m, int64_t n, float* out) {
+  __shared__ float sh[256];
+  float v = 3.4e38f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v = fminf(v, m[i]);
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fminf(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+wave_status wave_set_model(wave_ctx* c, const float* m) {
+  if (!c || !m) return fail(c, WAVE_EINVAL, "null model");
+  // min(m) via the wavefield buffer w[3] as temporary space (overwritten by any sweep anyway)
+  const int nb = 1024;
+  hipLaunchKernelGGL(k_min_reduce, dim3(nb), dim3(256), 0, c->stream, m, c->N, c->w[3]);
+  HIP_TRY(c, hipGetLastError());
+  std::vector<float> mins(nb);
+  HIP_TRY(c, hipMemcpyAsync(mins.data(), c->w[3], nb * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  float mn = *std::min_element(mins.begin(), mins.end());
+  if (!(mn > 0.0f) || !std::isfinite(mn)) return fail(c, WAVE_EINVAL, "model must be positive and finite");
+  const double cmax = 1.0 / std::sqrt((double)mn);
+  const double cfl = cfl_number(&c->d, cmax);
+  if (cfl > 1.0 + 1e-12) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "dt exceeds the stability limit by a factor %.4f (c_max %.1f m/s)", cfl, cmax);
+    return fail(c, WAVE_ECFL, buf);
+  }
+  hipLaunchKernelGGL(k_compute_b, grid1d(c->N), dim3(256), 0, c->stream, m, c->b, c->N, c->d.dt * c->d.dt);
+  HIP_TRY(c, hipGetLastError());
+  c->ck.valid = false;
+  return WAVE_OK;
+}
+
+wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t state_bytes, void* stream,
+                      wave_ctx** out) {
+  if (!out) return WAVE_EINVAL;
+  *out = nullptr;
+  std::string msg;
+  wave_status s = check_desc(d, msg);
+  if (s != WAVE_OK) return s;
+  if (!m || !state) return WAVE_EINVAL;
+  if (state_bytes < wave_state_bytes(d)) return WAVE_ENOMEM;
+  wave_ctx* c = new wave_ctx();
+  c->d = *d;
+  c->R = d->space_order / 2;
+  c->dim = d->ndim;
+  c->n0 = d->shape[0];
+  c->n1 = d->ndim == 3 ? d->shape[1] : 1;
+  c->n2 = d->ndim == 3 ? d->shape[2] : d->shape[1];
+  c->N = npts_of(d);
+  c->stream = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+      c->max_lds = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+    }
+  }
+  // coefficients: FP64 then rounded once
+  double cw[9];
+  fd_weights(d->space_order, cw);
+  double inv_h2[3] = {0, 0, 0};
+  for (int a = 0; a < d->ndim; ++a) inv_h2[a] = 1.0 / (d->spacing[a] * d->spacing[a]);
+  // axis slots: 0 = streamed (axis 0), 1 = y (3D axis 1), 2 = x (last axis)
+  const double ih_z = inv_h2[0], ih_y = d->ndim == 3 ? inv_h2[1] : 0.0, ih_x = inv_h2[d->ndim - 1];
+  c->C.c0 = (float)(cw[0] * (ih_z + ih_y + ih_x));
+  for (int j = 1; j <= c->R; ++j) {
+    c->C.w[0][j - 1] = (float)(cw[j] * ih_z);
+    c->C.w[1][j - 1] = (float)(cw[j] * ih_y);
+    c->C.w[2][j - 1] = (float)(cw[j] * ih_x);
+  }
+  // carve state
+  char* p = (char*)state;
+  c->b = (float*)p;
+  p += align_up(sizeof(float) * c->N);
+  for (int i = 0; i < 4; ++i) {
+    c->w[i] = (float*)p;
+    p += align_up(sizeof(float) * c->N);
+  }
+  const int64_t ext[3] = {c->n0, c->n1, c->n2};
+  float* tabs[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a == 1 && d->ndim == 2) {
+      tabs[a] = nullptr;
+      continue;
+    }
+    tabs[a] = (float*)p;
+    p += align_up(sizeof(float) * ext[a]);
+  }
+  c->stz = tabs[0];
+  c->sty = tabs[1];
+  c->stx = tabs[2];
+  // damping tables: st_a[i] = sigma_max (d_a(i)/nbl)^2 dt / 2 (FP64, rounded once)
+  for (int a = 0; a < 3; ++a) {
+    if (!tabs[a]) continue;
+    std::vector<float> t(ext[a], 0.0f);
+    if (d->nbl > 0) {
+      for (int64_t i = 0; i < ext[a]; ++i) {
+        int64_t dd = 0;
+        if (i < d->nbl) dd = d->nbl - i;
+        else if (i > ext[a] - 1 - d->nbl) dd = i - (ext[a] - 1 - d->nbl);
+        const double f = (double)dd / (double)d->nbl;
+        t[i] = (float)(d->sigma_max * f * f * d->dt / 2.0);
+      }
+    }
+    s = (wave_status)0;
+    if (hipMemcpyAsync(tabs[a], t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+      delete c;
+      return WAVE_EHIP;
+    }
+  }
+  const int T0 = d->time_tile == 0 ? -2 : d->time_tile;
+  s = apply_schedule(c, T0 == -2 ? -1 : T0, d->skew, d->tile_shape, d->zchunks);
+  if (s != WAVE_OK) {
+    delete c;
+    return s;
+  }
+  s = wave_set_model(c, m);
+  if (s != WAVE_OK) {
+    delete c;
+    return s;
+  }
+  if (T0 == -2) {
+    // default heuristic pick; wave_autotune refines it by measurement
+    int best = -1;
+    for (int T = std::min(4, tiled_tmax(c->R, c->dim, c->shape)); T >= 2; --T) {
+      Plan pl;
+      if (make_plan(c, KIND_TILED, T, pl) == WAVE_OK) {
+        best = T;
+        break;
+      }
+    }
+    c->T = best;
+    c->err.clear();
+  }
+  *out = c;
+  return WAVE_OK;
+}
+
+void wave_destroy(wave_ctx* c) { delete c; }
+
+size_t wave_scratch_bytes(const wave_ctx* c, int32_t nt, int32_t nsrc, int32_t nrec, int32_t K, int32_t adjoint) {
+  if (!c || nt < 0 || nsrc < 0 || nrec < 0 || K < 0) return 0;
+  return layout(c, nt, nsrc, nrec, K, adjoint).total;
+}
+
+wave_status wave_forward(wave_ctx* c, int32_t nt, int32_t nsrc, const double* src, const float* wav, int32_t nrec,
+                         const double* rec, float* rec_out, const float* u_init, float* u_final, int32_t K,
+                         void* scratch, size_t scratch_bytes) {
+  if (!c) return WAVE_EINVAL;
+  c->err.clear();
+  c->ck.valid = false;
+  if (nt < 0 || K < 0) return fail(c, WAVE_EINVAL, "negative nt or checkpoint interval");
+  wave_status s;
+  if ((s = validate_coords(c, nsrc, src)) || (s = validate_coords(c, nrec, rec))) return s;
+  if (nt > 0 && nsrc > 0 && !wav) return fail(c, WAVE_EINVAL, "null wavelet");
+  const Layout L = layout(c, nt, nsrc, nrec, K, 0);
+  if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  s = forward_core(c, nt, nsrc, src, wav, nrec, rec, rec_out, u_init, u_final, K, (char*)scratch, L);
+  if (s != WAVE_OK) return s;
+  if (K > 0 && !u_init) {
+    c->ck.valid = true;
+    c->ck.nt = nt;
+    c->ck.K = K;
+    c->ck.nsrc = nsrc;
+    c->ck.nrec = nrec;
+    c->ck.scratch = scratch;
+    c->ck.src.assign(src, src + (size_t)nsrc * c->dim);
+  }
+  return WAVE_OK;
+}
+
+wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const double* src, const float* wav,
+                              int32_t nrec, const double* rec, const float* resid, float* grad_m, float* grad_q,
+                              int32_t K, int32_t reuse, void* scratch, size_t scratch_bytes) {
+  if (!c) return WAVE_EINVAL;
+  c->err.clear();
+  if (nt < 0 || K < 1) return fail(c, WAVE_EINVAL, "need nt >= 0 and a checkpoint interval >= 1");
+  if (!grad_m) return fail(c, WAVE_EINVAL, "null grad_m");
+  if (nt > 0 && nrec > 0 && !resid) return fail(c, WAVE_EINVAL, "null residual");
+  wave_status s;
+  if ((s = validate_coords(c, nsrc, src)) || (s = validate_coords(c, nrec, rec))) return s;
+  if (nt > 0 && nsrc > 0 && !wav) return fail(c, WAVE_EINVAL, "null wavelet");
+  const Layout L = layout(c, nt, nsrc, nrec, K, 1);
+  if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  char* sc = (char*)scratch;
+  if (reuse) {
+    const bool ok = c->ck.valid && c->ck.nt == nt && c->ck.K == K && c->ck.nsrc == nsrc && c->ck.scratch == scratch &&
+                    std::equal(c->ck.src.begin(), c->ck.src.end(), src);
+    if (!ok) return fail(c, WAVE_ESTATE, "no matching checkpoints from a preceding forward");
+  } else {
+    s = forward_core(c, nt, nsrc, src, wav, 0, nullptr, nullptr, nullptr, nullptr, K, sc, L);
+    if (s != WAVE_OK) return s;
+  }
+  c->ck.valid = false;
+  // source table (for injection during recompute and for grad_q sampling)
+  PointTable PS, PR;
+  build_points(c, nsrc, src, PS);
+  build_points(c, nrec, rec, PR);
+  DevPoints DS, DR;
+  std::vector<char> h1, h2;
+  char* cur = sc + L.tab_src;
+  if ((s = upload_points(c, PS, cur, DS, h1))) return s;
+  cur = sc + L.tab_rec;
+  if ((s = upload_points(c, PR, cur, DR, h2))) return s;
+  float* table = (float*)(sc + L.inj);
+  if (PS.npts > 0) {
+    hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * PS.npts), dim3(256), 0, c->stream, wav, nsrc, nt,
+                       DS.pt_ptr, DS.pt_src, DS.pt_w, PS.npts, 1.0f, table);
+    HIP_TRY(c, hipGetLastError());
+  }
+  float* atab = (float*)(sc + L.adj_inj);
+  if (PR.npts > 0) {
+    const float inv_dt2 = (float)(1.0 / (c->d.dt * c->d.dt));
+    hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * PR.npts), dim3(256), 0, c->stream, resid, nrec, nt,
+                       DR.pt_ptr, DR.pt_src, DR.pt_w, PR.npts, inv_dt2, atab);
+    HIP_TRY(c, hipGetLastError());
+  }
+  float* asmp = (float*)(sc + L.adj_smp);
+  if (grad_q && PS.npts > 0) {
+    if ((s = fill(c, asmp, (int64_t)nt * PS.npts, 0.0f))) return s;
+  }
+  float* ck = (float*)(sc + L.ckpt);
+  float* hist = (float*)(sc + L.hist);
+  float* aw = (float*)(sc + L.adj_w);
+  Waves U, M;
+  for (int i = 0; i < 4; ++i) {
+    U.buf[i] = c->w[i];
+    M.buf[i] = aw + (size_t)i * c->N;
+  }
+  if ((s = fill(c, M.C(), c->N, 0.0f))) return s;
+  if ((s = fill(c, M.P(), c->N, 0.0f))) return s;
+  if ((s = fill(c, grad_m, c->N, 0.0f))) return s;
+  Window fw{&DS, table, nullptr, nullptr, hist, 0, nullptr};
+  Window bw{PR.npts > 0 ? &DR : nullptr, atab, (grad_q && PS.npts > 0) ? &DS : nullptr, asmp, hist, 0, grad_m};
+  for (int seg = L.nseg - 1; seg >= 0; --seg) {
+    const int c0 = seg * K, c1 = std::min(nt, c0 + K);
+    U.cur = 0;
+    U.prev = 1;
+    if ((s = copy(c, ck + (size_t)seg * 2 * c->N, U.C(), c->N))) return s;
+    if ((s = copy(c, ck + (size_t)seg * 2 * c->N + c->N, U.P(), c->N))) return s;
+    fw.hist_base = c0 + 1;
+    if ((s = run_steps(c, U, c0, c1 - c0, 1, fw))) return s;
+    bw.hist_base = c0 + 1;
+    if ((s = run_steps(c, M, c1 - 1, c1 - c0, -1, bw))) return s;
+  }
+  if (grad_q && nsrc > 0) {
+    if (PS.npts > 0) {
+      hipLaunchKernelGGL(k_reduce_samples, grid1d((int64_t)nt * nsrc), dim3(256), 0, c->stream, asmp, PS.npts, nt,
+                         DS.pos_ptr, DS.corner_pt, DS.corner_w, nsrc, (float)(c->d.dt * c->d.dt), grad_q);
+      HIP_TRY(c, hipGetLastError());
+    } else if ((s = fill(c, grad_q, (int64_t)nt * nsrc, 0.0f))) {
+      return s;
+    }
+  }
+  return WAVE_OK;
+}
+
+wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const int32_t* nsrc,
+                       const double* const* src_xyz, const float* const* wavelet_dev, const int32_t* nrec,
+                       const double* const* rec_xyz, float* const* rec_dev, const float* const* resid_dev,
+                       float* const* grad_m_dev, int32_t ckpt_every, void* const* scratch_dev,
+                       const size_t* scratch_bytes) {
+  (void)ctxs; (void)nshots; (void)nt; (void)nsrc; (void)src_xyz; (void)wavelet_dev; (void)nrec; (void)rec_xyz;
+  (void)rec_dev; (void)resid_dev; (void)grad_m_dev; (void)ckpt_every; (void)scratch_dev; (void)scratch_bytes;
+  return WAVE_EUNSUPPORTED;
+}
+
+wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, void* scratch,
+                          size_t scratch_bytes, double* best) {
+  if (!c || trial_steps < 1 || repeats < 1) return WAVE_EINVAL;
+  const Layout L = layout(c, trial_steps, 0, 0, 0, 0);
+  if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  struct Cand { int T, skew, shape, zc; };
+  std::vector<Cand> cands;
+  cands.push_back({-1, c->R, c->shape ? c->shape : 1, 0});
+  const int shapes[2] = {1, 2};
+  for (int si = 0; si < (c->dim == 3 ? 2 : 1); ++si) {
+    const int sh = c->dim == 3 ? shapes[si] : 0;
+    const int tm = std::min<int>(max_T > 0 ? max_T : 8, tiled_tmax(c->R, c->dim, sh ? sh : 0));
+    for (int T = 1; T <= tm; ++T) cands.push_back({T, c->R, sh, 0});
+  }
+  const int oT = c->T, os = c->skew, osh = c->shape, oz = c->zchunks;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  double best_t = 1e300;
+  Cand bc{oT, os, osh, oz};
+  for (const Cand& k : cands) {
+    if (apply_schedule(c, k.T, k.skew, k.shape ? k.shape : 1, k.zc) != WAVE_OK) continue;
+    double tmin = 1e300;
+    bool ok = true;
+    for (int r = 0; r < repeats + 1 && ok; ++r) {
+      hipEventRecord(e0, c->stream);
+      if (forward_core(c, trial_steps, 0, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, (char*)scratch,
+                       L) != WAVE_OK)
+        ok = false;
+      hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) ok = false;
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) tmin = std::min(tmin, (double)ms * 1e-3);   // first run is a warm-up
+    }
+    if (ok && tmin < best_t) {
+      best_t = tmin;
+      bc = k;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->err.clear();
+  wave_status s = apply_schedule(c, bc.T, bc.skew, bc.shape ? bc.shape : 1, bc.zc);
+  if (s != WAVE_OK) {
+    c->T = oT; c->skew = os; c->shape = osh; c->zchunks = oz;
+    return s;
+  }
+  if (best) *best = best_t / trial_steps;
+  return WAVE_OK;
+}
+
+// ----------------------------------------------------------- estimators
+
+double wave_ai_naive(double ai_space, int32_t t_t) { return ai_space * (double)t_t; }
+
+double wave_ai_tight(double ai_space, int32_t t_t, int32_t n, const double* D, const double* delta, const double* tile,
+                     double omega) {
+  if (n < 1 || n > 8 || t_t < 1 || !D || !delta || !tile) return NAN;
+  double F[8], bfrac[8];
+  double vol = 1.0;
+  for (int i = 0; i < n; ++i) vol *= D[i];
+  for (int i = 0; i < n; ++i) {
+    double f = 2.0 * delta[i];
+    for (int j = 0; j < i; ++j) f *= tile[j];
+    for (int k = i + 1; k < n; ++k) f *= D[k];
+    F[i] = f * (double)t_t;                                   // time-tiling: faces grow t_t-fold
+    bfrac[i] = 2.0 * (delta[i] / D[i]) * std::floor(D[i] / tile[i]);
+  }
+  // deepest face that still does not fit: i* = max{i : F_i >= omega}
+  int istar = -1;
+  for (int i = 0; i < n; ++i)
+    if (F[i] >= omega) istar = i;
+  double frac = 0.0;
+  if (istar >= 1) {
+    for (int j = 0; j < istar; ++j) frac = frac + bfrac[j] - frac * bfrac[j];   // union of B_1..B_{i*-1}
+  } else if (istar == 0) {
+    frac = (F[0] - omega) * std::floor(D[0] / tile[0]) / vol;
+  }
+  return wave_ai_naive(ai_space, t_t) / (1.0 + frac);
+}
+
+double wave_flops_per_point(int32_t ndim, int32_t so, int32_t damped) {
+  // centre product, per axis per pair one add + one FMA, forcing add, (1 - st),
+  // 2u, two FMAs; inside the layer one add, the reciprocal and one multiply.
+  const double r = so / 2;
+  return 1.0 + 3.0 * ndim * r + 7.0 + (damped ? 3.0 : 0.0);
+}
+
+double wave_bytes_per_point(int32_t T, int32_t mode) {
+  // compulsory traffic per point-update: read u^n, u^{n-1}, b once per launch,
+  // write one level (in place, T <= 1) or two levels (ping-pong, T >= 2);
+  // history +4 B (write or read); imaging gradient +8 B (read-modify-write).
+  const double Tt = T < 1 ? 1.0 : (double)T;
+  double base = (T <= 1) ? 16.0 : 20.0 / Tt;
+  if (mode == 1) base += 4.0;
+  if (mode == 2) base += 4.0 + 8.0;
+  return base;
+}
+
+}  // extern "C"

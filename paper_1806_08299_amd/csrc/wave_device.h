@@ -1,0 +1,127 @@
+// wave_device.h -- device-side building blocks shared by every sweep kernel.
+//
+// The paper's correctness criterion for time-tiling (evaluation chapter,
+// "Functional correctness") is bitwise equality with the untiled sweep: every
+// value must be reached through the same expression, only in another order of
+// points.  Here that is guaranteed by construction: every kernel (untiled,
+// time-tiled, forward, adjoint) evaluates a grid point through
+// `wave_point<R, HAS_Y>()` below, with explicit fused multiply-adds and
+// contraction disabled for the whole library (-ffp-contract=off), so the
+// arithmetic per point is one fixed sequence of IEEE operations no matter how
+// the points are scheduled.
+//
+// The update is the leapfrog step for  m u_tt + m sigma u_t = lap u + q
+// written with b = dt^2/m and st = sigma dt / 2:
+//   u^{n+1} = [ b (L u^n + f) + 2 u^n - (1 - st) u^{n-1} ] / (1 + st)
+// (f = sum_s w q for the forward sweep; sum_r w dd / dt^2 for the adjoint,
+// which runs the same step backwards in time because the step's blocks are
+// symmetric).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wavett {
+
+constexpr int kMaxR = 8;
+
+// Stencil weights in FP32: c0 = c_0 * sum_a h_a^-2, w[a][j-1] = c_j / h_a^2.
+// Axis slots: 0 = streamed axis (z), 1 = middle axis (y, 3D only), 2 = unit
+// stride axis (x).
+struct Coefs {
+  float c0;
+  float w[3][kMaxR];
+};
+
+// One grid point.  zm[j-1] = u(z-j), zp[j-1] = u(z+j), likewise y and x.
+// Operation order: centre, then axis z pairs j=1..R, axis y, axis x; then the
+// forcing; then the time update.  Never reorder: the tiled/untiled bitwise
+// equality rests on this sequence.
+template <int R, bool HAS_Y>
+__device__ __forceinline__ float wave_point(const Coefs& C, float uc,
+                                            const float* zm, const float* zp,
+                                            const float* ym, const float* yp,
+                                            const float* xm, const float* xp,
+                                            float uprev, float b, float st, float f) {
+  float lap = C.c0 * uc;
+#pragma unroll
+  for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[0][j], zm[j] + zp[j], lap);
+  if (HAS_Y) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[1][j], ym[j] + yp[j], lap);
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[2][j], xm[j] + xp[j], lap);
+  const float t = lap + f;
+  const float keep = 1.0f - st;
+  const float a = __builtin_fmaf(-keep, uprev, 2.0f * uc);
+  const float num = __builtin_fmaf(b, t, a);
+  // Inside the absorbing layer divide by (1 + st) through the hardware
+  // reciprocal; elsewhere st == 0 and the value is returned untouched.
+  return (st != 0.0f) ? num * __builtin_amdgcn_rcpf(1.0f + st) : num;
+}
+
+// Gradient contribution of one adjoint step (imaging condition):
+//   g <- g - u^j ((1+st) mu^{j-1} - 2 mu^j + (1-st) mu^{j+1})
+// accumulated one time step at a time, in decreasing j, by every kernel.
+__device__ __forceinline__ float image_step(float g, float u, float st,
+                                            float mu_new, float mu_cur, float mu_old) {
+  float t = (1.0f + st) * mu_new;
+  t = __builtin_fmaf(-2.0f, mu_cur, t);
+  t = __builtin_fmaf(1.0f - st, mu_old, t);
+  return __builtin_fmaf(-u, t, g);
+}
+
+// Points where a forcing term enters (sources forward, receivers in the
+// adjoint) or where values are sampled (receivers forward, sources in the
+// adjoint).  Unique grid points sorted by (z, y, x); zptr is a CSR index over
+// the streamed axis (n0 + 1 entries).  `table`/`samp` are [step][npts].
+struct PointSet {
+  const int32_t* zptr;
+  const int32_t* y;
+  const int32_t* x;
+  int32_t npts;
+};
+
+// Kernel modes.
+enum : int { MODE_FWD = 0, MODE_HIST = 1, MODE_ADJ = 2 };
+
+// Everything a sweep launch needs (passed by value).
+struct SweepArgs {
+  Coefs C;
+  int32_t n0, n1, n2;          // grid (2D: n1 == 1)
+  int64_t s1, s0;              // strides of axis 1 and axis 0 (elements)
+  const float* cur;            // level "n" (forward) or mu^{m} (adjoint)
+  const float* prev;           // level n-1 / mu^{m+1}
+  float* outA;                 // new top level (n+T)
+  float* outB;                 // level n+T-1 (may be null for in-place T=1)
+  const float* b;              // dt^2 / m
+  const float* stz;            // st tables per axis: st = (stz[z] + sty[y]) + stx[x]
+  const float* sty;
+  const float* stx;
+  int32_t has_damp;            // 0: st == 0 everywhere (tables may be null)
+  PointSet inj;                // forcing points
+  const float* inj_table;      // [steps][inj.npts]
+  PointSet smp;                // sampled points
+  float* smp_out;              // [steps][smp.npts] or null
+  int32_t step0;               // step index produced by stage 1
+  int32_t dir;                 // +1 forward, -1 adjoint: stage k produces step0 + dir (k-1)
+  float* hist;                 // MODE_HIST: written; MODE_ADJ: read.  [slot][N]
+  int32_t hist_base;           // slot = level - hist_base (level = step + 1)
+  float* grad;                 // MODE_ADJ: gradient accumulator [N]
+  // tiling
+  int32_t skew;                // halo per fused step on the tiled axes
+  int32_t core_y, core_x;      // core tile extents
+  int32_t tiles_x;             // number of tiles along x (blockIdx.x = ty*tiles_x + tx)
+  int32_t zchunk;              // streamed-axis segment length per block (blockIdx.y)
+};
+
+// Step of stage k (1-based) of a launch.
+__device__ __forceinline__ int stage_step(const SweepArgs& A, int k) {
+  return A.step0 + A.dir * (k - 1);
+}
+
+__device__ __forceinline__ float ldg_or0(const float* p, bool ok) {
+  return ok ? __builtin_nontemporal_load(p) : 0.0f;
+}
+
+}  // namespace wavett

@@ -1,0 +1,331 @@
+"""Python binding of the C ABI in include/wave.h (libwavett.so).
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels of
+libwavett.so.  PyTorch provides device memory (tensors whose data pointers
+are handed to the library) and the stream (torch's current HIP stream).  The
+functions keep the C names; ``WaveOp`` bundles a context with its buffers and
+``WaveFn`` is the ``torch.autograd.Function`` that makes the modelled
+receiver traces differentiable with respect to the model m and the wavelet.
+
+If the library has not been built the first call raises: there is no CPU or
+pure-PyTorch fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwavett.so")
+
+WAVE_OK = 0
+STATUS = {0: "WAVE_OK", -1: "WAVE_EINVAL", -2: "WAVE_ESKEW", -3: "WAVE_ECFL", -4: "WAVE_ENOMEM",
+          -5: "WAVE_EHIP", -6: "WAVE_ESTATE", -7: "WAVE_EUNSUPPORTED"}
+
+
+class WaveError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class wave_desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("space_order", ctypes.c_int32),
+                ("shape", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3),
+                ("dt", ctypes.c_double), ("nbl", ctypes.c_int32), ("sigma_max", ctypes.c_double),
+                ("time_tile", ctypes.c_int32), ("skew", ctypes.c_int32),
+                ("tile_shape", ctypes.c_int32), ("zchunks", ctypes.c_int32)]
+
+
+def make_desc(shape, spacing, dt, space_order, nbl=0, sigma_max=0.0, time_tile=-1, skew=0,
+              tile_shape=0, zchunks=0) -> wave_desc:
+    d = wave_desc()
+    shape = tuple(int(s) for s in shape)
+    d.ndim = len(shape)
+    d.space_order = int(space_order)
+    sp = tuple(float(h) for h in (spacing if np.ndim(spacing) else (spacing,) * len(shape)))
+    for a in range(3):
+        d.shape[a] = shape[a] if a < len(shape) else 1
+        d.spacing[a] = sp[a] if a < len(shape) else 1.0
+    d.dt = float(dt)
+    d.nbl = int(nbl)
+    d.sigma_max = float(sigma_max)
+    d.time_tile = int(time_tile)
+    d.skew = int(skew)
+    d.tile_shape = int(tile_shape)
+    d.zchunks = int(zchunks)
+    return d
+
+
+_lib = None
+P = ctypes.c_void_p
+
+
+def lib():
+    """Load libwavett.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libwavett.so not built: run __graft_entry__.build() "
+                              "(or python -m paper_1806_08299_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64, sz, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+        sig = {
+            "wave_state_bytes": (sz, [P]),
+            "wave_init": (i32, [P, P, P, sz, P, ctypes.POINTER(P)]),
+            "wave_set_model": (i32, [P, P]),
+            "wave_set_schedule": (i32, [P, i32, i32, i32, i32]),
+            "wave_get_schedule": (i32, [P, P, P, P, P]),
+            "wave_scratch_bytes": (sz, [P, i32, i32, i32, i32, i32]),
+            "wave_forward": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, P, sz]),
+            "wave_adjoint_grad": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, i32, P, sz]),
+            "wave_batch": (i32, [P, i32, i32, P, P, P, P, P, P, P, P, i32, P, P]),
+            "wave_autotune": (i32, [P, i32, i32, i32, P, sz, P]),
+            "wave_ai_naive": (dbl, [dbl, i32]),
+            "wave_ai_tight": (dbl, [dbl, i32, i32, P, P, P, dbl]),
+            "wave_flops_per_point": (dbl, [i32, i32, i32]),
+            "wave_bytes_per_point": (dbl, [i32, i32]),
+            "wave_strerror": (ctypes.c_char_p, [i32]),
+            "wave_last_error": (ctypes.c_char_p, [P]),
+            "wave_destroy": (None, [P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, ctx=None):
+    if status != WAVE_OK:
+        msg = lib().wave_last_error(ctx).decode() if ctx else ""
+        if not msg:
+            msg = lib().wave_strerror(status).decode()
+        raise WaveError(status, msg)
+
+
+def _dptr(t: Optional[torch.Tensor], dtype=torch.float32):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError("expected a contiguous %s device tensor" % dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _hptr(a: Optional[np.ndarray]):
+    if a is None or a.size == 0:
+        return None
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _coords(x, ndim):
+    if x is None:
+        return np.zeros((0, ndim), dtype=np.float64)
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1, ndim))
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ C names
+
+def wave_state_bytes(desc: wave_desc) -> int:
+    return int(lib().wave_state_bytes(ctypes.byref(desc)))
+
+
+def wave_init(desc: wave_desc, m: torch.Tensor, state: torch.Tensor, stream=None):
+    out = ctypes.c_void_p()
+    st = lib().wave_init(ctypes.byref(desc), _dptr(m), ctypes.c_void_p(state.data_ptr()),
+                         state.numel() * state.element_size(), _stream(stream), ctypes.byref(out))
+    _check(st)
+    return out
+
+
+def wave_set_model(ctx, m: torch.Tensor):
+    _check(lib().wave_set_model(ctx, _dptr(m)), ctx)
+
+
+def wave_set_schedule(ctx, time_tile: int, skew: int = 0, tile_shape: int = 0, zchunks: int = 0):
+    _check(lib().wave_set_schedule(ctx, time_tile, skew, tile_shape, zchunks), ctx)
+
+
+def wave_get_schedule(ctx):
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().wave_get_schedule(ctx, *[ctypes.byref(x) for x in v]), ctx)
+    return tuple(x.value for x in v)
+
+
+def wave_scratch_bytes(ctx, nt: int, nsrc: int, nrec: int, ckpt_every: int = 0, adjoint: int = 0) -> int:
+    return int(lib().wave_scratch_bytes(ctx, nt, nsrc, nrec, ckpt_every, adjoint))
+
+
+def wave_forward(ctx, nt, src_xyz, wavelet, rec_xyz, rec_out, u_init, u_final, ckpt_every, scratch, ndim):
+    src = _coords(src_xyz, ndim)
+    rec = _coords(rec_xyz, ndim)
+    st = lib().wave_forward(ctx, nt, src.shape[0], _hptr(src), _dptr(wavelet), rec.shape[0], _hptr(rec),
+                            _dptr(rec_out), _dptr(u_init), _dptr(u_final), ckpt_every,
+                            ctypes.c_void_p(scratch.data_ptr()), scratch.numel() * scratch.element_size())
+    _check(st, ctx)
+
+
+def wave_adjoint_grad(ctx, nt, src_xyz, wavelet, rec_xyz, resid, grad_m, grad_wavelet, ckpt_every, reuse,
+                      scratch, ndim):
+    src = _coords(src_xyz, ndim)
+    rec = _coords(rec_xyz, ndim)
+    st = lib().wave_adjoint_grad(ctx, nt, src.shape[0], _hptr(src), _dptr(wavelet), rec.shape[0], _hptr(rec),
+                                 _dptr(resid), _dptr(grad_m), _dptr(grad_wavelet), ckpt_every, int(reuse),
+                                 ctypes.c_void_p(scratch.data_ptr()), scratch.numel() * scratch.element_size())
+    _check(st, ctx)
+
+
+def wave_autotune(ctx, trial_steps, repeats, max_T, scratch):
+    best = ctypes.c_double()
+    st = lib().wave_autotune(ctx, trial_steps, repeats, max_T, ctypes.c_void_p(scratch.data_ptr()),
+                             scratch.numel() * scratch.element_size(), ctypes.byref(best))
+    _check(st, ctx)
+    return best.value
+
+
+def wave_ai_naive(ai_space: float, t_t: int) -> float:
+    return float(lib().wave_ai_naive(ai_space, t_t))
+
+
+def wave_ai_tight(ai_space, t_t, D, delta, tile, omega) -> float:
+    n = len(D)
+    arr = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in (D, delta, tile)]
+    return float(lib().wave_ai_tight(ai_space, t_t, n, *[_hptr(a) for a in arr], float(omega)))
+
+
+def wave_flops_per_point(ndim, space_order, damped=0) -> float:
+    return float(lib().wave_flops_per_point(ndim, space_order, damped))
+
+
+def wave_bytes_per_point(time_tile, mode=0) -> float:
+    return float(lib().wave_bytes_per_point(time_tile, mode))
+
+
+def wave_destroy(ctx):
+    if ctx:
+        lib().wave_destroy(ctx)
+
+
+# ------------------------------------------------------------------ convenience
+
+class WaveOp:
+    """A context plus the device buffers it needs (allocated as torch tensors)."""
+
+    def __init__(self, shape, spacing, dt, space_order, m: torch.Tensor, nbl=0, sigma_max=0.0,
+                 time_tile=-1, skew=0, tile_shape=0, zchunks=0, device="cuda"):
+        self.desc = make_desc(shape, spacing, dt, space_order, nbl, sigma_max, time_tile, skew,
+                              tile_shape, zchunks)
+        self.shape = tuple(int(s) for s in shape)
+        self.ndim = len(self.shape)
+        self.device = torch.device(device)
+        nbytes = wave_state_bytes(self.desc)
+        if nbytes == 0:
+            raise WaveError(-1, "invalid descriptor")
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.m = m.to(self.device, torch.float32).contiguous()
+        self.ctx = wave_init(self.desc, self.m, self.state)
+        self._scratch = None
+
+    def __del__(self):
+        try:
+            wave_destroy(self.ctx)
+        except Exception:
+            pass
+
+    @property
+    def npts(self):
+        return int(np.prod(self.shape))
+
+    def scratch(self, nbytes: int) -> torch.Tensor:
+        if self._scratch is None or self._scratch.numel() < nbytes:
+            self._scratch = None
+            self._scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self._scratch
+
+    def set_model(self, m: torch.Tensor):
+        self.m = m.to(self.device, torch.float32).contiguous()
+        wave_set_model(self.ctx, self.m)
+
+    def set_schedule(self, time_tile, skew=0, tile_shape=0, zchunks=0):
+        wave_set_schedule(self.ctx, time_tile, skew, tile_shape, zchunks)
+
+    def schedule(self):
+        return wave_get_schedule(self.ctx)
+
+    def forward(self, nt, src_xyz=None, wavelet=None, rec_xyz=None, u_init=None, want_final=False,
+                ckpt_every=0, adjoint_scratch=False):
+        src = _coords(src_xyz, self.ndim)
+        rec = _coords(rec_xyz, self.ndim)
+        if wavelet is not None:
+            wavelet = wavelet.to(self.device, torch.float32).contiguous()
+        rec_out = torch.empty((nt, rec.shape[0]), dtype=torch.float32, device=self.device) if rec.shape[0] else None
+        fin = torch.empty((2,) + self.shape, dtype=torch.float32, device=self.device) if want_final else None
+        nb = wave_scratch_bytes(self.ctx, nt, src.shape[0], rec.shape[0], ckpt_every, 1 if adjoint_scratch else 0)
+        sc = self.scratch(nb)
+        wave_forward(self.ctx, nt, src, wavelet, rec, rec_out, u_init, fin, ckpt_every, sc, self.ndim)
+        return rec_out, fin
+
+    def adjoint_grad(self, nt, src_xyz, wavelet, rec_xyz, resid, ckpt_every, want_grad_wavelet=True, reuse=False):
+        src = _coords(src_xyz, self.ndim)
+        rec = _coords(rec_xyz, self.ndim)
+        gm = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        gq = torch.empty((nt, src.shape[0]), dtype=torch.float32, device=self.device) \
+            if (want_grad_wavelet and src.shape[0]) else None
+        nb = wave_scratch_bytes(self.ctx, nt, src.shape[0], rec.shape[0], ckpt_every, 1)
+        if reuse and (self._scratch is None or self._scratch.numel() < nb):
+            reuse = False
+        sc = self.scratch(nb)
+        resid = resid.to(self.device, torch.float32).contiguous()
+        if wavelet is not None:
+            wavelet = wavelet.to(self.device, torch.float32).contiguous()
+        try:
+            wave_adjoint_grad(self.ctx, nt, src, wavelet, rec, resid, gm, gq, ckpt_every, 1 if reuse else 0,
+                              sc, self.ndim)
+        except WaveError as e:
+            if not (reuse and e.status == -6):
+                raise
+            wave_adjoint_grad(self.ctx, nt, src, wavelet, rec, resid, gm, gq, ckpt_every, 0, sc, self.ndim)
+        return gm, gq
+
+
+class WaveFn(torch.autograd.Function):
+    """rec = WaveFn.apply(m, wavelet, op, src_xyz, rec_xyz, ckpt_every).
+
+    Forward models the receiver traces [nt, nrec] for squared slowness m and
+    source wavelet [nt, nsrc]; backward returns (dL/dm, dL/dwavelet) from the
+    time-reversed adjoint sweep with the imaging condition, recomputing the
+    forward in checkpointed segments of ckpt_every steps."""
+
+    @staticmethod
+    def forward(ctx, m, wavelet, op: WaveOp, src_xyz, rec_xyz, ckpt_every: int = 50):
+        op.set_model(m.detach())
+        nt = wavelet.shape[0]
+        rec, _ = op.forward(nt, src_xyz, wavelet.detach(), rec_xyz, ckpt_every=ckpt_every, adjoint_scratch=True)
+        ctx.op = op
+        ctx.src_xyz = src_xyz
+        ctx.rec_xyz = rec_xyz
+        ctx.ckpt_every = ckpt_every
+        ctx.save_for_backward(wavelet.detach())
+        return rec
+
+    @staticmethod
+    def backward(ctx, grad_rec):
+        (wavelet,) = ctx.saved_tensors
+        op = ctx.op
+        nt = wavelet.shape[0]
+        gm, gq = op.adjoint_grad(nt, ctx.src_xyz, wavelet, ctx.rec_xyz, grad_rec.contiguous(), ctx.ckpt_every,
+                                 want_grad_wavelet=ctx.needs_input_grad[1], reuse=True)
+        return gm, gq, None, None, None, None

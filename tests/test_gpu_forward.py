@@ -1,0 +1,249 @@
+"""GPU parity of the forward sweep (untiled and time-tiled) through the C ABI.
+
+* untiled GPU (FP32) vs the FP64 oracle: relative L2 <= 1e-5 on the final two
+  levels and on the receiver traces;
+* time-tiled GPU vs untiled GPU: bitwise, for every fused depth T, tile shape,
+  skew and axis-0 segmentation available for the order (the paper's
+  functional-correctness criterion);
+* edge cases: ragged grids smaller than a tile, partial last windows, nt = 0,
+  points on nodes / on the boundary / outside the grid, 2D, every order.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import waveinputs as wi
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _op(w, **kw):
+    from paper_1806_08299_amd import WaveOp
+    return WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).cuda(), nbl=w.nbl,
+                  sigma_max=w.sigma_max, **kw)
+
+
+def _run(op, w, nt=None, want_final=True):
+    nt = w.nt if nt is None else nt
+    wav = torch.from_numpy(np.ascontiguousarray(w.wavelet[:nt])).cuda()
+    rec, fin = op.forward(nt, w.src_xyz, wav, w.rec_xyz, want_final=want_final)
+    torch.cuda.synchronize()
+    return (rec.cpu().numpy() if rec is not None else None), (fin.cpu().numpy() if fin is not None else None)
+
+
+def _oracle(w, nt=None):
+    nt = w.nt if nt is None else nt
+    g = oracle.Grid(w.shape, w.spacing, w.dt, w.so, nbl=w.nbl, sigma_max=w.sigma_max)
+    return oracle.forward(g, w.m.astype(np.float64), nt, w.src_xyz, w.wavelet[:nt].astype(np.float64),
+                          w.rec_xyz, want_final=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a).astype(np.float64) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+TMAX = {3: {1: [0, 8, 5, 3, 3, 2, 2, 1, 1], 2: [0, 8, 6, 4, 3, 2, 2, 1, 1]},
+        2: {0: [0, 8, 8, 6, 5, 4, 3, 3, 2]}}
+
+
+def _schedules(R, ndim):
+    """Every (T, tile shape) built for radius R; the caller drops those the
+    device cannot hold (WAVE_EUNSUPPORTED from set_schedule)."""
+    out = []
+    for shape, tab in TMAX[ndim].items():
+        for T in range(1, tab[R] + 1):
+            out.append((T, shape))
+    return out
+
+
+def _try_schedule(op, T, shape, skew=0, zchunks=0):
+    from paper_1806_08299_amd import WaveError
+    try:
+        op.set_schedule(T, skew, shape, zchunks)
+        return True
+    except WaveError as e:
+        if e.status != -7:
+            raise
+        print("schedule T=%d shape=%d unavailable: %s" % (T, shape, e))
+        return False
+
+
+# --------------------------------------------------------------------------- C1
+
+@pytest.fixture(scope="module")
+def c1_ref():
+    w = wi.c1()
+    return w, _oracle(w)
+
+
+def test_c1_untiled_matches_oracle(c1_ref):
+    w, ref = c1_ref
+    op = _op(w, time_tile=-1)
+    rec, fin = _run(op, w)
+    assert np.abs(fin).max() > 1e-3, "solution is (nearly) zero"
+    assert np.all(np.isfinite(fin))
+    for lev in (0, 1):
+        assert rel(fin[lev], ref["final"][lev]) <= TOL, lev
+    assert rel(rec, ref["rec"]) <= TOL
+
+
+@pytest.mark.parametrize("T", [1, 2, 4])
+def test_c1_tiled_bitwise_equals_untiled(c1_ref, T):
+    w, ref = c1_ref
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    for shape in (1, 2):
+        op.set_schedule(T, 0, shape, 0)
+        rec_t, fin_t = _run(op, w)
+        assert np.array_equal(fin_t, fin_u), (T, shape)
+        assert np.array_equal(rec_t, rec_u), (T, shape)
+    assert rel(fin_t[0], ref["final"][0]) <= TOL
+
+
+# --------------------------------------------------------------------------- every order
+
+def _small(so, shape, nbl, seed, nt=24, nsrc=2, nrec=7):
+    rng = np.random.default_rng(seed)
+    nd = len(shape)
+    h = tuple(float(v) for v in rng.uniform(8.0, 12.0, size=nd))
+    c = rng.uniform(1500, 3000, size=shape)
+    m = wi.to_slowness2(c)
+    dt = 0.35 * min(h) / 3000.0
+    src = np.array([[rng.uniform(0.2, shape[a] - 1.2) * h[a] for a in range(nd)] for _ in range(nsrc)])
+    # receivers within a few cells of a source, so that every trace is non-zero within nt steps
+    rec = np.array([[np.clip(src[i % nsrc][a] / h[a] + rng.uniform(-5.0, 5.0), 0.0, shape[a] - 1.0) * h[a]
+                     for a in range(nd)] for i in range(nrec)])
+    wav = rng.standard_normal((nt, nsrc)).astype(np.float32)
+    u0 = 1e-3 * rng.standard_normal(shape)
+    return wi.Workload("small", tuple(shape), h, dt, so, nt, nbl, 60.0 if nbl else 0.0, m, src, wav, rec,
+                       extra={"u0": u0})
+
+
+@pytest.mark.parametrize("so", [2, 4, 6, 8, 10, 12, 14, 16])
+def test_every_order_3d_oracle_and_bitwise(so):
+    R = so // 2
+    shape = (4 * R + 7, 83, 71)   # ragged: not multiples of any tile
+    w = _small(so, shape, nbl=3, seed=so)
+    ref = _oracle(w)
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    assert rel(fin_u[0], ref["final"][0]) <= TOL
+    assert rel(rec_u, ref["rec"]) <= TOL
+    ran = 0
+    for T, shp in _schedules(R, 3):
+        if not _try_schedule(op, T, shp):
+            continue
+        ran += 1
+        rec_t, fin_t = _run(op, w)
+        assert np.array_equal(fin_t, fin_u), (so, T, shp)
+        assert np.array_equal(rec_t, rec_u), (so, T, shp)
+    assert ran >= 2
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 16])
+def test_every_order_2d_oracle_and_bitwise(so):
+    R = so // 2
+    shape = (57, 1100)   # axis 1 longer than one 2D tile
+    w = _small(so, shape, nbl=4, seed=100 + so, nt=30)
+    ref = _oracle(w)
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    assert rel(fin_u[0], ref["final"][0]) <= TOL
+    assert rel(rec_u, ref["rec"]) <= TOL
+    for T, shp in _schedules(R, 2):
+        if not _try_schedule(op, T, shp):
+            continue
+        rec_t, fin_t = _run(op, w)
+        assert np.array_equal(fin_t, fin_u), (so, T)
+        assert np.array_equal(rec_t, rec_u), (so, T)
+
+
+@pytest.mark.parametrize("skew_extra,zchunks", [(1, 0), (2, 3), (0, 1), (0, 5)])
+def test_skew_and_segmentation_bitwise(skew_extra, zchunks):
+    w = _small(8, (45, 70, 90), nbl=5, seed=7)
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    op.set_schedule(2, 4 + skew_extra, 1, zchunks)
+    rec_t, fin_t = _run(op, w)
+    assert np.array_equal(fin_t, fin_u)
+    assert np.array_equal(rec_t, rec_u)
+
+
+def test_partial_windows_and_nt_edge_cases():
+    w = _small(4, (30, 40, 50), nbl=2, seed=9, nt=7)
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    op.set_schedule(4, 0, 1, 0)          # windows 4 + 3
+    rec_t, fin_t = _run(op, w)
+    assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u)
+    ref = _oracle(w)
+    assert rel(fin_u[0], ref["final"][0]) <= TOL
+    # nt = 0: final state is the (zero) initial state, no traces
+    rec0, fin0 = _run(op, w, nt=0)
+    assert np.array_equal(fin0, np.zeros_like(fin0))
+
+
+def test_tiny_grid_and_points_on_boundary_or_outside():
+    so = 8
+    shape = (9, 5, 13)                    # smaller than every tile in every axis
+    w = _small(so, shape, nbl=0, seed=11, nt=12)
+    h = w.spacing
+    w.src_xyz = np.array([[4 * h[0], 2 * h[1], 6 * h[2]],              # on a node
+                          [0.0, 0.0, 0.0],                             # on the corner node
+                          [8 * h[0], 4.5 * h[1], 12 * h[2]]])          # on the far faces
+    w.wavelet = np.random.default_rng(3).standard_normal((12, 3)).astype(np.float32)
+    w.rec_xyz = np.array([[3.3 * h[0], 1.1 * h[1], 7.7 * h[2]],
+                          [-50.0, 1.0, 1.0],                           # outside: zero trace
+                          [8 * h[0], 4 * h[1], 12 * h[2]]])
+    ref = _oracle(w)
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    assert rel(fin_u[0], ref["final"][0]) <= TOL
+    assert np.array_equal(rec_u[:, 1], np.zeros(12, np.float32))
+    assert rel(rec_u, ref["rec"]) <= TOL
+    for T, shp in _schedules(4, 3):
+        if not _try_schedule(op, T, shp):
+            continue
+        rec_t, fin_t = _run(op, w)
+        assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u), (T, shp)
+
+
+def test_initial_state_and_resume_bitwise():
+    w = _small(6, (40, 33, 66), nbl=3, seed=13, nt=20)
+    op = _op(w, time_tile=3)
+    u0 = torch.from_numpy(np.stack([w.extra["u0"], 0.5 * w.extra["u0"]]).astype(np.float32)).cuda()
+    wav = torch.from_numpy(w.wavelet).cuda()
+    rec_full, fin_full = op.forward(20, w.src_xyz, wav, w.rec_xyz, u_init=u0, want_final=True)
+    rec_a, fin_a = op.forward(9, w.src_xyz, wav[:9].contiguous(), w.rec_xyz, u_init=u0, want_final=True)
+    rec_b, fin_b = op.forward(11, w.src_xyz, wav[9:].contiguous(), w.rec_xyz, u_init=fin_a, want_final=True)
+    assert torch.equal(torch.cat([rec_a, rec_b]), rec_full)
+    assert torch.equal(fin_b, fin_full)
+    g = oracle.Grid(w.shape, w.spacing, w.dt, w.so, nbl=w.nbl, sigma_max=w.sigma_max)
+    ref = oracle.forward(g, w.m.astype(np.float64), 20, w.src_xyz, w.wavelet.astype(np.float64), w.rec_xyz,
+                         u_init=u0.cpu().numpy().astype(np.float64), want_final=True)
+    assert rel(fin_full.cpu().numpy()[0], ref["final"][0]) <= TOL
+
+
+def test_error_paths():
+    from paper_1806_08299_amd import WaveError
+    w = _small(8, (20, 20, 20), nbl=0, seed=1, nt=4)
+    with pytest.raises(WaveError) as e:
+        _op(w, time_tile=2, skew=3)
+    assert e.value.status == -2                       # WAVE_ESKEW
+    bad = _small(8, (20, 20, 20), nbl=0, seed=1, nt=4)
+    bad.dt = w.dt * 1.5 / 0.35                        # CFL far above the limit
+    with pytest.raises(WaveError) as e:
+        _op(bad)
+    assert e.value.status == -3                       # WAVE_ECFL
+    op = _op(w, time_tile=-1)
+    with pytest.raises(WaveError) as e:
+        op.set_schedule(8, 0, 1, 0)                   # T beyond what is built for so8
+    assert e.value.status == -7
+    from paper_1806_08299_amd.wave import wave_forward
+    tiny = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(WaveError) as e:
+        wave_forward(op.ctx, 4, None, None, None, None, None, None, 0, tiny, 3)
+    assert e.value.status == -4                       # WAVE_ENOMEM
