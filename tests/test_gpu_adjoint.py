@@ -1,0 +1,169 @@
+"""GPU parity of the adjoint sweep, the imaging-condition gradient, the
+checkpointed recompute and the autograd wrapper (through the C ABI).
+
+Bars: gradient and source-side adjoint within relative L2 1e-4 of the FP64
+oracle (FP32 accumulation over every step of two sweeps); time-tiled adjoint
+bitwise equal to the untiled adjoint; gradient bitwise independent of the
+checkpoint interval (recompute reproduces the forward exactly); dot-product
+test to FP32 accuracy.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import waveinputs as wi
+
+pytestmark = pytest.mark.gpu
+
+TOL_GRAD = 1e-4
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a).astype(np.float64) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def _problem(so=8, shape=(36, 41, 47), nbl=4, nt=40, seed=0, nsrc=2, nrec=9):
+    rng = np.random.default_rng(seed)
+    nd = len(shape)
+    h = (10.0,) * nd
+    c_true = wi.smooth_random_velocity(shape, seed=seed, sigma_cells=3.0, cmin=1800.0, cmax=2600.0)
+    m_true = wi.to_slowness2(c_true)
+    m0 = wi.to_slowness2(np.full(shape, 2000.0))
+    dt = 0.35 * 10.0 / 2600.0
+    src = np.array([[rng.uniform(nbl + 2, shape[a] - nbl - 3) * h[a] for a in range(nd)] for _ in range(nsrc)])
+    rec = np.array([[np.clip(src[i % nsrc][a] / h[a] + rng.uniform(-8, 8), 0, shape[a] - 1) * h[a]
+                     for a in range(nd)] for i in range(nrec)])
+    wav = np.stack([wi.ricker(nt, dt, 30.0, t0=0.02 + 0.01 * s) for s in range(nsrc)], axis=1)
+    smax = wi.sigma_max_estimate(2600.0, nbl, 10.0) if nbl else 0.0
+    g = oracle.Grid(shape, h, dt, so, nbl=nbl, sigma_max=smax)
+    return dict(shape=shape, h=h, dt=dt, so=so, nbl=nbl, smax=smax, nt=nt, src=src, rec=rec, wav=wav,
+                m_true=m_true, m0=m0, g=g)
+
+
+def _op(P, m, **kw):
+    from paper_1806_08299_amd import WaveOp
+    return WaveOp(P["shape"], P["h"], P["dt"], P["so"], torch.from_numpy(m).cuda(), nbl=P["nbl"],
+                  sigma_max=P["smax"], **kw)
+
+
+@pytest.fixture(scope="module")
+def prob():
+    P = _problem()
+    g = P["g"]
+    dobs = oracle.forward(g, P["m_true"].astype(np.float64), P["nt"], P["src"], P["wav"], P["rec"])["rec"]
+    fw = oracle.forward(g, P["m0"].astype(np.float64), P["nt"], P["src"], P["wav"], P["rec"], want_hist=True)
+    resid = (fw["rec"] - dobs).astype(np.float32)
+    ref = oracle.adjoint(g, P["m0"].astype(np.float64), P["nt"], resid.astype(np.float64), hist=fw["hist"],
+                         src_xyz=P["src"], rec_xyz=P["rec"], want_grad_q=True)
+    P.update(dobs=dobs, resid=resid, ref=ref)
+    return P
+
+
+def _grad(op, P, K, reuse=False):
+    wav = torch.from_numpy(P["wav"]).cuda()
+    resid = torch.from_numpy(P["resid"]).cuda()
+    if reuse:
+        op.forward(P["nt"], P["src"], wav, P["rec"], ckpt_every=K, adjoint_scratch=True)
+    gm, gq = op.adjoint_grad(P["nt"], P["src"], wav, P["rec"], resid, K, reuse=reuse)
+    torch.cuda.synchronize()
+    return gm.cpu().numpy(), gq.cpu().numpy()
+
+
+def test_gradient_matches_oracle(prob):
+    op = _op(prob, prob["m0"], time_tile=-1)
+    gm, gq = _grad(op, prob, K=prob["nt"])
+    assert np.abs(gm).max() > 0 and np.all(np.isfinite(gm))
+    assert rel(gm, prob["ref"]["grad_m"]) <= TOL_GRAD
+    assert rel(gq, prob["ref"]["grad_q"]) <= TOL_GRAD
+
+
+@pytest.mark.parametrize("T,shape", [(1, 1), (2, 1), (3, 1), (2, 2), (3, 2)])
+def test_tiled_adjoint_bitwise_equals_untiled(prob, T, shape):
+    op = _op(prob, prob["m0"], time_tile=-1)
+    gm_u, gq_u = _grad(op, prob, K=13)
+    op.set_schedule(T, 0, shape, 0)
+    gm_t, gq_t = _grad(op, prob, K=13)
+    assert np.array_equal(gm_t, gm_u)
+    assert np.array_equal(gq_t, gq_u)
+
+
+def test_checkpoint_interval_does_not_change_gradient(prob):
+    op = _op(prob, prob["m0"], time_tile=2)
+    base, bq = _grad(op, prob, K=prob["nt"])          # whole history in one segment
+    for K in (1, 5, 7, 16):
+        gm, gq = _grad(op, prob, K=K)
+        assert np.array_equal(gm, base), K
+        assert np.array_equal(gq, bq), K
+    gm, gq = _grad(op, prob, K=8, reuse=True)          # checkpoints from the preceding forward
+    assert np.array_equal(gm, base) and np.array_equal(gq, bq)
+
+
+def test_reuse_without_forward_is_rejected(prob):
+    from paper_1806_08299_amd import WaveError
+    from paper_1806_08299_amd.wave import wave_adjoint_grad, wave_scratch_bytes
+    op = _op(prob, prob["m0"], time_tile=2)
+    nb = wave_scratch_bytes(op.ctx, prob["nt"], 2, 9, 10, 1)
+    sc = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    gm = torch.empty(prob["shape"], device="cuda")
+    with pytest.raises(WaveError) as e:
+        wave_adjoint_grad(op.ctx, prob["nt"], prob["src"], torch.from_numpy(prob["wav"]).cuda(), prob["rec"],
+                          torch.from_numpy(prob["resid"]).cuda(), gm, None, 10, 1, sc, 3)
+    assert e.value.status == -6
+
+
+def test_dot_product_fp32(prob):
+    """<F q, dd> = <q, F^T dd> with F the (linear in q) forward map."""
+    op = _op(prob, prob["m0"], time_tile=2)
+    rng = np.random.default_rng(5)
+    q = rng.standard_normal(prob["wav"].shape).astype(np.float32)
+    dd = rng.standard_normal(prob["resid"].shape).astype(np.float32)
+    rec, _ = op.forward(prob["nt"], prob["src"], torch.from_numpy(q).cuda(), prob["rec"])
+    _, gq = op.adjoint_grad(prob["nt"], prob["src"], torch.from_numpy(q).cuda(), prob["rec"],
+                            torch.from_numpy(dd).cuda(), 10)
+    lhs = float(np.sum(rec.cpu().numpy().astype(np.float64) * dd))
+    rhs = float(np.sum(q.astype(np.float64) * gq.cpu().numpy()))
+    assert abs(lhs - rhs) / abs(lhs) < 1e-5
+
+
+def test_autograd_function(prob):
+    from paper_1806_08299_amd import WaveFn
+    op = _op(prob, prob["m0"], time_tile=2)
+    m = torch.from_numpy(prob["m0"]).cuda().requires_grad_(True)
+    wav = torch.from_numpy(prob["wav"]).cuda().requires_grad_(True)
+    dobs = torch.from_numpy(prob["dobs"].astype(np.float32)).cuda()
+    rec = WaveFn.apply(m, wav, op, prob["src"], prob["rec"], 10)
+    loss = 0.5 * ((rec - dobs) ** 2).sum()
+    loss.backward()
+    gm = m.grad.cpu().numpy()
+    assert rel(gm, prob["ref"]["grad_m"]) <= TOL_GRAD
+    assert rel(wav.grad.cpu().numpy(), prob["ref"]["grad_q"]) <= 2e-4   # residual itself from FP32 traces
+    # directional central difference of the loss in FP32 (loose: FP32 noise)
+    dm = torch.from_numpy((prob["m0"] * np.random.default_rng(2).uniform(-1, 1, prob["shape"])).astype(np.float32)).cuda()
+    eps = 1e-2
+
+    def J(mm):
+        r = WaveFn.apply(mm, wav.detach(), op, prob["src"], prob["rec"], 10)
+        return 0.5 * float(((r.double() - dobs.double()) ** 2).sum())
+
+    fd = (J(m.detach() + eps * dm) - J(m.detach() - eps * dm)) / (2 * eps)
+    gd = float((m.grad.double() * dm.double()).sum())
+    assert abs(fd - gd) / abs(gd) < 5e-3
+
+
+def test_gradient_2d_every_order():
+    for so in (2, 4, 8, 16):
+        P = _problem(so=so, shape=(50, 61), nbl=5, nt=30, seed=so, nsrc=1, nrec=6)
+        g = P["g"]
+        fw = oracle.forward(g, P["m0"].astype(np.float64), P["nt"], P["src"], P["wav"], P["rec"], want_hist=True)
+        resid = fw["rec"].astype(np.float32)
+        ref = oracle.adjoint(g, P["m0"].astype(np.float64), P["nt"], resid.astype(np.float64), hist=fw["hist"],
+                             src_xyz=P["src"], rec_xyz=P["rec"], want_grad_q=True)
+        P["resid"] = resid
+        op = _op(P, P["m0"], time_tile=-1)
+        gm_u, gq_u = _grad(op, P, K=7)
+        assert rel(gm_u, ref["grad_m"]) <= TOL_GRAD, so
+        assert rel(gq_u, ref["grad_q"]) <= TOL_GRAD, so
+        op.set_schedule(2, 0, 0, 0)
+        gm_t, gq_t = _grad(op, P, K=7)
+        assert np.array_equal(gm_t, gm_u) and np.array_equal(gq_t, gq_u), so
