@@ -14,6 +14,7 @@
 
 #include "../../include/wave.h"
 #include "wave_helpers.h"
+#include "wave_kernels.h"
 #include "wave_launch.h"
 
 using namespace wavett;
@@ -321,8 +322,7 @@ wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p) {
     p.core_y = (c->dim == 3) ? bs.ey - 2 * H : 1;
     if (p.core_x < 1 || p.core_y < 1)
       return fail(c, WAVE_EUNSUPPORTED, "halo (skew * T) leaves no core in the extended tile");
-    const int ry = (c->dim == 3) ? c->R : 0;
-    p.lds = (size_t)T * (bs.ey + 2 * ry) * (bs.ex + 2 * c->R) * sizeof(float);
+    p.lds = tiled_lds_bytes(c->R, T, bs.ey, bs.ex, c->dim == 3);
     if (p.lds > c->max_lds) return fail(c, WAVE_EUNSUPPORTED, "tile needs more LDS than a workgroup can hold");
   }
   const int64_t ny = (c->dim == 3) ? c->n1 : 1;
@@ -332,6 +332,13 @@ wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p) {
   int zc = c->zchunks > 0 ? c->zchunks : auto_zchunks(c, base, kind, T);
   zc = (int)std::min<int64_t>(zc, c->n0);
   p.zchunk = (int)((c->n0 + zc - 1) / zc);
+  // A workgroup addresses its segment of planes (chunk plus pipeline halo)
+  // through one buffer descriptor with 32-bit offsets below kSegMax.
+  const int64_t plane_bytes = c->n1 * c->n2 * (int64_t)sizeof(float);
+  const int64_t halo = 2LL * ((kind == KIND_UNTILED ? 0 : T) + 1) * c->R;
+  const int64_t max_chunk = (int64_t)kSegMax / plane_bytes - halo;
+  if (max_chunk < 1) return fail(c, WAVE_EUNSUPPORTED, "grid plane too large for one buffer segment");
+  if (p.zchunk > max_chunk) p.zchunk = (int)max_chunk;
   p.zc = (int)((c->n0 + p.zchunk - 1) / p.zchunk);
   return WAVE_OK;
 }

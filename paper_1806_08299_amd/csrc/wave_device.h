@@ -115,13 +115,20 @@ struct SweepArgs {
   int32_t zchunk;              // streamed-axis segment length per block (blockIdx.y)
 };
 
+// LDS planes of the tiled kernel: each is (EX + 2R) x (EY + 2R_y) floats; one
+// set of T planes, doubled (one barrier per plane instead of two) when both
+// sets fit in the 160 KiB of LDS a gfx950 workgroup may use.
+constexpr int tiled_plane_floats(int R, int EY, int EX, bool HY) { return (EX + 2 * R) * (EY + 2 * (HY ? R : 0)); }
+constexpr int tiled_nbuf(int R, int T, int EY, int EX, bool HY) {
+  return (2 * T * tiled_plane_floats(R, EY, EX, HY) * 4 <= 160 * 1024) ? 2 : 1;
+}
+constexpr size_t tiled_lds_bytes(int R, int T, int EY, int EX, bool HY) {
+  return (size_t)tiled_nbuf(R, T, EY, EX, HY) * T * tiled_plane_floats(R, EY, EX, HY) * 4;
+}
+
 // Step of stage k (1-based) of a launch.
 __device__ __forceinline__ int stage_step(const SweepArgs& A, int k) {
   return A.step0 + A.dir * (k - 1);
-}
-
-__device__ __forceinline__ float ldg_or0(const float* p, bool ok) {
-  return ok ? __builtin_nontemporal_load(p) : 0.0f;
 }
 
 }  // namespace wavett
