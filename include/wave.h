@@ -72,8 +72,8 @@ typedef struct wave_desc {
   int32_t time_tile;     /* T >= 1 fused steps per launch; 0 = autotune at init;
                             -1 = untiled single-step sweep (the reference schedule) */
   int32_t skew;          /* halo per fused step on the tiled axes; 0 = r; must be >= r */
-  int32_t tile_shape;    /* 0 = auto; 1 = 64x64 extended tile (1024 threads);
-                            2 = 32x64 extended tile (512 threads) (3D only) */
+  int32_t tile_shape;    /* 3D tiled sweep: 0 = auto; 1 = 64x64 extended tile;
+                            2 = 32x64 extended tile (both 512 threads).  2D: ignored */
   int32_t zchunks;       /* segments of axis 0 per launch; 0 = auto */
 } wave_desc;
 
@@ -176,6 +176,11 @@ wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, i
 double wave_ai_naive(double ai_space, int32_t t_t);
 double wave_ai_tight(double ai_space, int32_t t_t, int32_t ndim, const double* D, const double* delta,
                      const double* tile, double omega);
+
+/* Largest fused depth T built for this order, dimension and tile shape
+ * (3D: tile_shape 1 or 2; 2D: ignored); 0 if none.  Bounded by the register
+ * file: every fused level keeps a (so+1)-plane window per column.  Host-only. */
+int32_t wave_tiled_max_depth(int32_t space_order, int32_t ndim, int32_t tile_shape);
 
 /* Flops per point-update of the sweep (adds + multiplies, FMA = 2) for order
  * so in ndim dimensions, and compulsory HBM bytes per point-update of the

@@ -31,7 +31,7 @@ FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH, "-ffp-contract=
 
 def sources():
     srcs = [os.path.join(CSRC, "wave_api.cpp")]
-    srcs += [os.path.join(CSRC, "wave_r%d.hip" % r) for r in range(1, 9)]
+    srcs += [os.path.join(CSRC, "wave_r%d_m%d.hip" % (r, m)) for r in range(1, 9) for m in range(3)]
     return srcs
 
 
@@ -48,8 +48,9 @@ def build(jobs: int = 0, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
     srcs = sources()
-    # largest units first
-    srcs.sort(key=lambda s: (0 if "wave_r1" in s or "wave_r2" in s else 1))
+    # largest units first (unrolled register rings: radius 4, 3, 2, then the rest)
+    cost = {"wave_r4": 0, "wave_r3": 1, "wave_r2": 2}
+    srcs.sort(key=lambda s: cost.get(os.path.basename(s)[:7], 3))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()

@@ -30,9 +30,6 @@ struct wave_ctx {
   // device state (carved from the caller's buffer)
   float* b = nullptr;
   float* w[4] = {nullptr, nullptr, nullptr, nullptr};
-  float* stz = nullptr;
-  float* sty = nullptr;
-  float* stx = nullptr;
   hipStream_t stream = nullptr;
   // schedule: T == -1 untiled kernel, T >= 1 tiled kernel
   int T = -1, skew = 0, shape = 1, zchunks = 0;
@@ -227,6 +224,7 @@ struct DevPoints {
   const int32_t* pt_src = nullptr;
   const float* pt_w = nullptr;
   int npos = 0;
+  int zlo = 0, zhi = 0;   // planes holding points: [zlo, zhi)
 };
 
 size_t table_bytes_bound(int64_t n0, int npos, int nd) {
@@ -266,6 +264,15 @@ wave_status upload_points(wave_ctx* c, const PointTable& P, char*& cursor, DevPo
   D.pt_src = (const int32_t*)(base + o_ts);
   D.pt_w = (const float*)(base + o_tw);
   D.npos = P.npos;
+  D.zlo = D.zhi = 0;
+  if (P.npts > 0) {
+    int64_t z = 0;
+    while (P.zptr[z + 1] == 0) ++z;
+    D.zlo = (int)z;
+    z = c->n0 - 1;
+    while (P.zptr[z] == P.npts) --z;
+    D.zhi = (int)z + 1;
+  }
   return WAVE_OK;
 }
 
@@ -332,13 +339,6 @@ wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p) {
   int zc = c->zchunks > 0 ? c->zchunks : auto_zchunks(c, base, kind, T);
   zc = (int)std::min<int64_t>(zc, c->n0);
   p.zchunk = (int)((c->n0 + zc - 1) / zc);
-  // A workgroup addresses its segment of planes (chunk plus pipeline halo)
-  // through one buffer descriptor with 32-bit offsets below kSegMax.
-  const int64_t plane_bytes = c->n1 * c->n2 * (int64_t)sizeof(float);
-  const int64_t halo = 2LL * ((kind == KIND_UNTILED ? 0 : T) + 1) * c->R;
-  const int64_t max_chunk = (int64_t)kSegMax / plane_bytes - halo;
-  if (max_chunk < 1) return fail(c, WAVE_EUNSUPPORTED, "grid plane too large for one buffer segment");
-  if (p.zchunk > max_chunk) p.zchunk = (int)max_chunk;
   p.zc = (int)((c->n0 + p.zchunk - 1) / p.zchunk);
   return WAVE_OK;
 }
@@ -353,9 +353,9 @@ SweepArgs base_args(const wave_ctx* c) {
   A.s0 = (int64_t)A.n1 * c->n2;
   A.b = c->b;
   A.has_damp = (c->d.nbl > 0 && c->d.sigma_max > 0.0) ? 1 : 0;
-  A.stz = c->stz;
-  A.sty = (c->dim == 3) ? c->sty : nullptr;
-  A.stx = c->stx;
+  A.nbl = c->d.nbl;
+  A.st_coef = A.has_damp ? (float)(c->d.sigma_max * c->d.dt / (2.0 * (double)c->d.nbl * (double)c->d.nbl)) : 0.0f;
+  A.inj_zlo = A.inj_zhi = A.smp_zlo = A.smp_zhi = 0;
   A.skew = c->skew;
   A.dir = 1;
   return A;
@@ -408,13 +408,17 @@ wave_status run_steps(wave_ctx* c, Waves& W, int step0, int steps, int dir, cons
     SweepArgs A = base_args(c);
     A.cur = W.C();
     A.prev = W.P();
-    if (win.inj) {
+    if (win.inj && win.inj->set.npts > 0) {
       A.inj = win.inj->set;
       A.inj_table = win.inj_table;
+      A.inj_zlo = win.inj->zlo;
+      A.inj_zhi = win.inj->zhi;
     }
-    if (win.smp) {
+    if (win.smp && win.smp->set.npts > 0 && win.smp_out) {
       A.smp = win.smp->set;
       A.smp_out = win.smp_out;
+      A.smp_zlo = win.smp->zlo;
+      A.smp_zhi = win.smp->zhi;
     }
     A.hist = win.hist;
     A.hist_base = win.hist_base;
@@ -564,7 +568,7 @@ BlockShape block_shape(int kind, int dim, int shape) {
   if (dim == 2) return {4, 4, 1, 1024};
   if (kind == KIND_UNTILED) return {4, 4, 16, 64};
   if (shape == 2) return {8, 4, 32, 64};
-  return {16, 4, 64, 64};
+  return {8, 8, 64, 64};
 }
 
 int tiled_tmax(int R, int dim, int shape) {
@@ -575,17 +579,17 @@ int tiled_tmax(int R, int dim, int shape) {
 
 hipError_t launch_sweep(int R, int kind, int T, int dim, int mode, int shape, const SweepArgs& A, dim3 grid,
                         size_t lds, hipStream_t s) {
+  if (mode < 0 || mode > 2) return hipErrorInvalidValue;
+#define WAVE_CASE(RR)                                                                  \
+  case RR:                                                                             \
+    return mode == 0 ? launch_sweep_r##RR##_m0(kind, T, dim, shape, A, grid, lds, s)  \
+         : mode == 1 ? launch_sweep_r##RR##_m1(kind, T, dim, shape, A, grid, lds, s)  \
+                     : launch_sweep_r##RR##_m2(kind, T, dim, shape, A, grid, lds, s);
   switch (R) {
-    case 1: return launch_sweep_r1(kind, T, dim, mode, shape, A, grid, lds, s);
-    case 2: return launch_sweep_r2(kind, T, dim, mode, shape, A, grid, lds, s);
-    case 3: return launch_sweep_r3(kind, T, dim, mode, shape, A, grid, lds, s);
-    case 4: return launch_sweep_r4(kind, T, dim, mode, shape, A, grid, lds, s);
-    case 5: return launch_sweep_r5(kind, T, dim, mode, shape, A, grid, lds, s);
-    case 6: return launch_sweep_r6(kind, T, dim, mode, shape, A, grid, lds, s);
-    case 7: return launch_sweep_r7(kind, T, dim, mode, shape, A, grid, lds, s);
-    case 8: return launch_sweep_r8(kind, T, dim, mode, shape, A, grid, lds, s);
+    WAVE_CASE(1) WAVE_CASE(2) WAVE_CASE(3) WAVE_CASE(4) WAVE_CASE(5) WAVE_CASE(6) WAVE_CASE(7) WAVE_CASE(8)
     default: return hipErrorInvalidValue;
   }
+#undef WAVE_CASE
 }
 
 }  // namespace wavett
@@ -617,7 +621,6 @@ size_t wave_state_bytes(const wave_desc* d) {
   const int64_t N = npts_of(d);
   size_t o = align_up(sizeof(float) * N);          // b
   o += 4 * align_up(sizeof(float) * N);             // wavefields
-  for (int a = 0; a < d->ndim; ++a) o += align_up(sizeof(float) * d->shape[a]);
   return o;
 }
 
@@ -741,38 +744,6 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
   for (int i = 0; i < 4; ++i) {
     c->w[i] = (float*)p;
     p += align_up(sizeof(float) * c->N);
-  }
-  const int64_t ext[3] = {c->n0, c->n1, c->n2};
-  float* tabs[3];
-  for (int a = 0; a < 3; ++a) {
-    if (a == 1 && d->ndim == 2) {
-      tabs[a] = nullptr;
-      continue;
-    }
-    tabs[a] = (float*)p;
-    p += align_up(sizeof(float) * ext[a]);
-  }
-  c->stz = tabs[0];
-  c->sty = tabs[1];
-  c->stx = tabs[2];
-  // damping tables: st_a[i] = sigma_max (d_a(i)/nbl)^2 dt / 2 (FP64, rounded once)
-  for (int a = 0; a < 3; ++a) {
-    if (!tabs[a]) continue;
-    std::vector<float> t(ext[a], 0.0f);
-    if (d->nbl > 0) {
-      for (int64_t i = 0; i < ext[a]; ++i) {
-        int64_t dd = 0;
-        if (i < d->nbl) dd = d->nbl - i;
-        else if (i > ext[a] - 1 - d->nbl) dd = i - (ext[a] - 1 - d->nbl);
-        const double f = (double)dd / (double)d->nbl;
-        t[i] = (float)(d->sigma_max * f * f * d->dt / 2.0);
-      }
-    }
-    s = (wave_status)0;
-    if (hipMemcpyAsync(tabs[a], t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice, c->stream) != hipSuccess) {
-      delete c;
-      return WAVE_EHIP;
-    }
   }
   const int T0 = d->time_tile == 0 ? -2 : d->time_tile;
   s = apply_schedule(c, T0 == -2 ? -1 : T0, d->skew, d->tile_shape, d->zchunks);
@@ -984,6 +955,12 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
 }
 
 // ----------------------------------------------------------- estimators
+
+int32_t wave_tiled_max_depth(int32_t space_order, int32_t ndim, int32_t tile_shape) {
+  if (space_order < 2 || space_order > 16 || (space_order & 1) || (ndim != 2 && ndim != 3)) return 0;
+  if (ndim == 3 && tile_shape != 1 && tile_shape != 2) return 0;
+  return tiled_tmax(space_order / 2, ndim, ndim == 3 ? tile_shape : 0);
+}
 
 double wave_ai_naive(double ai_space, int32_t t_t) { return ai_space * (double)t_t; }
 

@@ -5,7 +5,7 @@
 // value must be reached through the same expression, only in another order of
 // points.  Here that is guaranteed by construction: every kernel (untiled,
 // time-tiled, forward, adjoint) evaluates a grid point through
-// `wave_point<R, HAS_Y>()` below, with explicit fused multiply-adds and
+// `wave_num<R, HAS_Y>()` and `wave_damp()` below, with explicit fused multiply-adds and
 // contraction disabled for the whole library (-ffp-contract=off), so the
 // arithmetic per point is one fixed sequence of IEEE operations no matter how
 // the points are scheduled.
@@ -32,16 +32,19 @@ struct Coefs {
   float w[3][kMaxR];
 };
 
-// One grid point.  zm[j-1] = u(z-j), zp[j-1] = u(z+j), likewise y and x.
-// Operation order: centre, then axis z pairs j=1..R, axis y, axis x; then the
-// forcing; then the time update.  Never reorder: the tiled/untiled bitwise
-// equality rests on this sequence.
+// One grid point, numerator of the update.  zm[j-1] = u(z-j), zp[j-1] = u(z+j),
+// likewise y and x.  Operation order: centre, then axis z pairs j=1..R, axis
+// y, axis x; then the forcing; then the time update.  Never reorder: the
+// tiled/untiled bitwise equality rests on this sequence.  `damped` and
+// `forced` are uniform over a launch or a plane and only skip operations that
+// cannot change the result there (a forcing of +0, a damping factor of 1).
 template <int R, bool HAS_Y>
-__device__ __forceinline__ float wave_point(const Coefs& C, float uc,
-                                            const float* zm, const float* zp,
-                                            const float* ym, const float* yp,
-                                            const float* xm, const float* xp,
-                                            float uprev, float b, float st, float f) {
+__device__ __forceinline__ float wave_num(const Coefs& C, float uc,
+                                          const float* zm, const float* zp,
+                                          const float* ym, const float* yp,
+                                          const float* xm, const float* xp,
+                                          float uprev, float b, float st, float f,
+                                          bool damped, bool forced) {
   float lap = C.c0 * uc;
 #pragma unroll
   for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[0][j], zm[j] + zp[j], lap);
@@ -51,12 +54,15 @@ __device__ __forceinline__ float wave_point(const Coefs& C, float uc,
   }
 #pragma unroll
   for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[2][j], xm[j] + xp[j], lap);
-  const float t = lap + f;
-  const float keep = 1.0f - st;
-  const float a = __builtin_fmaf(-keep, uprev, 2.0f * uc);
-  const float num = __builtin_fmaf(b, t, a);
-  // Inside the absorbing layer divide by (1 + st) through the hardware
-  // reciprocal; elsewhere st == 0 and the value is returned untouched.
+  const float t = forced ? lap + f : lap;
+  // with st == 0 the fused form equals 2u - u_prev exactly
+  const float a = damped ? __builtin_fmaf(-(1.0f - st), uprev, 2.0f * uc) : 2.0f * uc - uprev;
+  return __builtin_fmaf(b, t, a);
+}
+
+// Inside the absorbing layer divide by (1 + st) through the hardware
+// reciprocal; elsewhere (st == 0) the numerator is the result.
+__device__ __forceinline__ float wave_damp(float num, float st) {
   return (st != 0.0f) ? num * __builtin_amdgcn_rcpf(1.0f + st) : num;
 }
 
@@ -95,14 +101,17 @@ struct SweepArgs {
   float* outA;                 // new top level (n+T)
   float* outB;                 // level n+T-1 (may be null for in-place T=1)
   const float* b;              // dt^2 / m
-  const float* stz;            // st tables per axis: st = (stz[z] + sty[y]) + stx[x]
-  const float* sty;
-  const float* stx;
-  int32_t has_damp;            // 0: st == 0 everywhere (tables may be null)
+  // damping: st = (e(z) + e(y)) + e(x), e(i) = st_coef * d(i)^2 with d(i) the
+  // depth of index i inside the absorbing layer of width nbl along that axis
+  int32_t has_damp;            // 0: st == 0 everywhere
+  int32_t nbl;
+  float st_coef;               // sigma_max * dt / (2 nbl^2)
   PointSet inj;                // forcing points
   const float* inj_table;      // [steps][inj.npts]
+  int32_t inj_zlo, inj_zhi;    // planes holding forcing points: [inj_zlo, inj_zhi)
   PointSet smp;                // sampled points
   float* smp_out;              // [steps][smp.npts] or null
+  int32_t smp_zlo, smp_zhi;    // planes holding sampled points
   int32_t step0;               // step index produced by stage 1
   int32_t dir;                 // +1 forward, -1 adjoint: stage k produces step0 + dir (k-1)
   float* hist;                 // MODE_HIST: written; MODE_ADJ: read.  [slot][N]
@@ -124,6 +133,12 @@ constexpr int tiled_nbuf(int R, int T, int EY, int EX, bool HY) {
 }
 constexpr size_t tiled_lds_bytes(int R, int T, int EY, int EX, bool HY) {
   return (size_t)tiled_nbuf(R, T, EY, EX, HY) * T * tiled_plane_floats(R, EY, EX, HY) * 4;
+}
+
+// Damping term of index i along an axis of n points (layer nbl wide).
+__device__ __forceinline__ float damp_term(int i, int n, int nbl, float coef) {
+  const int d = max(max(nbl - i, i - (n - 1 - nbl)), 0);
+  return coef * (float)(d * d);
 }
 
 // Step of stage k (1-based) of a launch.

@@ -8,9 +8,9 @@
 // k_untiled  -- one time step per launch ("spatial tiling" in the paper's
 //               terms).  A workgroup owns a core tile of TY x TX columns and
 //               streams one segment of axis 0 through a (2R+1)-plane register
-//               window per column; the current plane plus an R-wide halo
-//               loaded from global memory sits in LDS for the axis-1/axis-2
-//               neighbours.  u^{n+1} overwrites u^{n-1} in place.
+//               window per column; the current plane plus an R-wide halo,
+//               loaded from global memory, sits in LDS for the neighbours along
+//               axes 1 and 2.  u^{n+1} overwrites u^{n-1} in place.
 //
 // k_tiled    -- T time steps per launch: the GPU form of the paper's
 //               time-tiling (implementation chapter, "Time-tiling").  Along
@@ -24,13 +24,25 @@
 //               after T stages the core is exact.  Each stage's input plane is
 //               staged in LDS; the z windows of every level live in registers.
 //
-// Memory access discipline (both kernels): all global traffic goes through
-// raw buffer instructions whose descriptor covers only the segment of planes
-// a workgroup may touch.  Out-of-grid columns and planes use offsets beyond
-// the descriptor's range, so the hardware returns 0 (the zero boundary
-// values) or drops the store -- no branches and no address arithmetic in 64
-// bits in the inner loop.  Every load is issued one plane ahead of its use.
+// Register windows.  The (2R+1)-plane window of every level is a ring in
+// registers: the z loop is unrolled by the window length and the ring's
+// rotation is a compile-time constant in each unrolled copy, so sliding the
+// window costs no moves (for 2R+1 > kMaxUnrollW the window is shifted).
+// Neighbours along axis 1 that belong to the same thread come from those
+// registers; only the others are read from LDS.
+//
+// Memory access discipline.  Global traffic goes through raw buffer
+// instructions.  Each plane access builds its descriptor with scalar ops (base
+// at that plane, one plane of records, or zero records when the plane is
+// outside the grid or outside what the workgroup may store), so the per-lane
+// offset is just the precomputed column offset, and out-of-grid columns carry
+// an offset beyond any plane: the hardware returns 0 for loads (the zero
+// boundary values) and drops stores.  Every load is issued one plane ahead of
+// its use.  Because b = dt^2/m also reads as 0 outside the grid, the update
+// there evaluates to exactly +0 with no select.
 #pragma once
+#include <utility>
+
 #include "wave_device.h"
 
 namespace wavett {
@@ -39,14 +51,19 @@ namespace wavett {
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
-// Offsets are bytes relative to a workgroup's segment base.  A segment is at
-// most kSegMax bytes (host-enforced); any offset component >= kOOB makes the
-// sum land outside every descriptor without wrapping 32 bits.
-constexpr uint32_t kSegMax = 0x40000000u;
-constexpr uint32_t kOOB = 0x40000000u;
+constexpr uint32_t kOOB = 0xFFFFFFF0u;   // column offset of an out-of-grid lane
+#ifndef WAVE_MAX_UNROLL_W
+#define WAVE_MAX_UNROLL_W 9
+#endif
+constexpr int kMaxUnrollW = WAVE_MAX_UNROLL_W;   // unroll the z loop by the window for 2R+1 <= this
 
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+// Descriptor of plane z of array p: empty unless lo <= z < hi.
+__device__ __forceinline__ rsrc_t plane(const float* p, int z, int lo, int hi, int64_t s0, uint32_t pbytes) {
+  const bool ok = z >= lo && z < hi;
+  return make_rsrc(p + (ok ? (int64_t)z * s0 : 0), ok ? pbytes : 0u);
 }
 // The b32 builtins move raw 32-bit words: reinterpret, never convert.
 __device__ __forceinline__ float bload(rsrc_t r, uint32_t off) {
@@ -64,7 +81,6 @@ __device__ __forceinline__ V cload(const V* p, int64_t i) {
   return ((const __attribute__((address_space(4))) V*)p)[i];
 }
 
-// Forcing value at column (y, x) among the points p0..p1 of the current plane.
 __device__ __forceinline__ float forcing_in(const SweepArgs& A, int p0, int p1, int y, int x, int step) {
   float f = 0.0f;
   for (int p = p0; p < p1; ++p) {
@@ -79,6 +95,14 @@ __device__ __forceinline__ void sample_in(const SweepArgs& A, int p0, int p1, in
     if (cload(A.smp.y, p) == y && cload(A.smp.x, p) == x) A.smp_out[(int64_t)step * A.smp.npts + p] = v;
 }
 
+// Whole-wave "any lane" test (uniform result).
+__device__ __forceinline__ bool wave_any(bool c) { return __builtin_amdgcn_ballot_w64(c) != 0; }
+
+template <typename F, int... Is>
+__device__ __forceinline__ void unroll_rot(F&& f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+
 // --------------------------------------------------------------- untiled sweep
 
 // Thread slot i of (wave w, lane l):  3D: (ly, lx) = (w*RY + i, l);
@@ -86,6 +110,8 @@ __device__ __forceinline__ void sample_in(const SweepArgs& A, int p0, int p1, in
 template <int R, int DIM, int MODE, int NW, int RY>
 __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
   constexpr bool HY = (DIM == 3);
+  constexpr int W = 2 * R + 1;
+  constexpr bool ROT = W <= kMaxUnrollW;
   constexpr int TY = HY ? NW * RY : 1;
   constexpr int TX = HY ? 64 : 64 * NW * RY;
   constexpr int RYH = HY ? R : 0;
@@ -95,37 +121,34 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
   constexpr int NH = (HY ? 2 * R * TX : 0) + 2 * R * TY;
   constexpr int NT = 64 * NW;
   constexpr int HPT = (NH + NT - 1) / NT;
-  __shared__ float lds[2 * PL];
+  constexpr int RSTEP = HY ? LDW : 64;   // LDS distance between a thread's rows
+  constexpr int PLB = PL + 1;            // one plane plus a spare slot for unused halo writes
+  __shared__ float lds[2 * PLB];
 
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int ty = blockIdx.x / A.tiles_x, tx = blockIdx.x % A.tiles_x;
   const int gy0 = ty * TY, gx0 = tx * TX;
   const int za = blockIdx.y * A.zchunk;
   const int zb = min(za + A.zchunk, A.n0);
-  const int zlo = max(0, za - R), zhi = min(A.n0, zb + R);
-  const uint32_t PS = (uint32_t)A.s0 * 4u;
-  const uint32_t seg = (uint32_t)(zhi - zlo) * PS;
-  const int64_t base = (int64_t)zlo * A.s0;
-  const rsrc_t rc = make_rsrc(A.cur + base, seg);
-  const rsrc_t rp = make_rsrc(A.prev + base, seg);
-  const rsrc_t rb = make_rsrc(A.b + base, seg);
-  const rsrc_t ro = make_rsrc(A.outA + base, seg);
-  auto zoff = [&](int z) -> uint32_t { return (z >= zlo && z < zhi) ? (uint32_t)(z - zlo) * PS : kOOB; };
+  const int n0 = A.n0;
+  const int64_t s0 = A.s0;
+  const uint32_t PB = (uint32_t)s0 * 4u;
 
+  // 3D: the rows of a thread are wave-uniform, so their damping terms are
+  // scalars; the axis-2 term is per lane.  2D: slots differ along axis 2.
   uint32_t col[RY];
-  int lid[RY], gy[RY], gx[RY];
-  float sty[RY], stx[RY];
+  float sty[RY], stx[HY ? 1 : RY];
+  const int lid0 = (HY ? wv * RY + RYH : 0) * LDW + (HY ? lane : wv * RY * 64 + lane) + R;
 #pragma unroll
   for (int i = 0; i < RY; ++i) {
     const int ly = HY ? wv * RY + i : 0;
     const int lx = HY ? lane : (wv * RY + i) * 64 + lane;
-    gy[i] = gy0 + ly;
-    gx[i] = gx0 + lx;
-    const bool in = gy[i] < A.n1 && gx[i] < A.n2;
-    col[i] = in ? (uint32_t)(gy[i] * (int)A.s1 + gx[i]) * 4u : kOOB;
-    lid[i] = (ly + RYH) * LDW + lx + R;
-    sty[i] = (A.has_damp && HY && in) ? A.sty[gy[i]] : 0.0f;
-    stx[i] = (A.has_damp && in) ? A.stx[gx[i]] : 0.0f;
+    const int gy = gy0 + ly, gx = gx0 + lx;
+    const bool in = gy < A.n1 && gx < A.n2;
+    col[i] = in ? (uint32_t)(gy * (int)A.s1 + gx) * 4u : kOOB;
+    sty[i] = (A.has_damp && HY) ? damp_term(gy, A.n1, A.nbl, A.st_coef) : 0.0f;
+    if (!HY || i == 0) stx[HY ? 0 : i] = A.has_damp ? damp_term(gx, A.n2, A.nbl, A.st_coef) : 0.0f;
   }
   uint32_t hcol[HPT];
   int hlid[HPT];
@@ -149,95 +172,135 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
     const int Y = gy0 + y, X = gx0 + x;
     const bool ok = valid && Y >= 0 && Y < A.n1 && X >= 0 && X < A.n2;
     hcol[h] = ok ? (uint32_t)(Y * (int)A.s1 + X) * 4u : kOOB;
-    // unused slots write the (never read) corner of the padded plane
-    hlid[h] = valid ? (y + RYH) * LDW + x + R : 0;
+    hlid[h] = valid ? (y + RYH) * LDW + x + R : PL;   // unused slots write the spare slot
   }
 
-  float zw[RY][2 * R + 1];
-#pragma unroll
-  for (int i = 0; i < RY; ++i) {
-    zw[i][0] = 0.0f;
-#pragma unroll
-    for (int j = 1; j <= 2 * R; ++j) zw[i][j] = bload(rc, zoff(za - R - 1 + j) + col[i]);
-  }
-  // prefetch registers for the next plane
+  // Window ring: logical plane j (0 oldest .. 2R newest) at rotation r lives
+  // in slot (j + r) % W.
+  float zw[RY][W];
   float pc[RY], pp[RY], pb[RY], ph[HPT];
+  {
 #pragma unroll
-  for (int i = 0; i < RY; ++i) {
-    pc[i] = bload(rc, zoff(za + R) + col[i]);
-    pp[i] = bload(rp, zoff(za) + col[i]);
-    pb[i] = bload(rb, zoff(za) + col[i]);
+    for (int j = 1; j <= 2 * R; ++j) {   // planes za-R .. za+R-1: logical 0..2R-1 at rotation 1
+      const rsrc_t r = plane(A.cur, za - R - 1 + j, 0, n0, s0, PB);
+#pragma unroll
+      for (int i = 0; i < RY; ++i) zw[i][j % W] = bload(r, col[i]);
+    }
+    const rsrc_t rc = plane(A.cur, za + R, 0, n0, s0, PB);
+    const rsrc_t rp = plane(A.prev, za, 0, n0, s0, PB);
+    const rsrc_t rb = plane(A.b, za, 0, n0, s0, PB);
+    const rsrc_t rh = plane(A.cur, za, 0, n0, s0, PB);
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+      zw[i][0] = 0.0f;
+      pc[i] = bload(rc, col[i]);
+      pp[i] = bload(rp, col[i]);
+      pb[i] = bload(rb, col[i]);
+    }
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) ph[h] = bload(rh, hcol[h]);
   }
-#pragma unroll
-  for (int h = 0; h < HPT; ++h) ph[h] = bload(rc, zoff(za) + hcol[h]);
 
   const int step = A.step0;
-  const int64_t N = (int64_t)A.n0 * A.s0;
-  for (int z = za; z < zb; ++z) {
+  const int64_t N = (int64_t)n0 * s0;
+  const int nit = zb - za;
+  // One plane; `rot` is the rotation after this iteration's push.
+  auto body = [&](int z, auto rotc) {
+    constexpr int rot = decltype(rotc)::value;
+    __builtin_amdgcn_sched_barrier(0);   // keep unrolled copies from overlapping (register pressure)
     float up[RY], bb[RY], hv[HPT];
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
-#pragma unroll
-      for (int j = 0; j < 2 * R; ++j) zw[i][j] = zw[i][j + 1];
-      zw[i][2 * R] = pc[i];
+      zw[i][(2 * R + rot) % W] = pc[i];
       up[i] = pp[i];
       bb[i] = pb[i];
     }
 #pragma unroll
     for (int h = 0; h < HPT; ++h) hv[h] = ph[h];
     {  // issue the next plane's loads before touching this plane's data
-      const uint32_t zc = zoff(z + 1 + R), z1 = zoff(z + 1);
+      const rsrc_t rc = plane(A.cur, z + 1 + R, 0, n0, s0, PB);
+      const rsrc_t rp = plane(A.prev, z + 1, 0, n0, s0, PB);
+      const rsrc_t rb = plane(A.b, z + 1, 0, n0, s0, PB);
+      const rsrc_t rh = plane(A.cur, z + 1, 0, n0, s0, PB);
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
-        pc[i] = bload(rc, zc + col[i]);
-        pp[i] = bload(rp, z1 + col[i]);
-        pb[i] = bload(rb, z1 + col[i]);
+        pc[i] = bload(rc, col[i]);
+        pp[i] = bload(rp, col[i]);
+        pb[i] = bload(rb, col[i]);
       }
 #pragma unroll
-      for (int h = 0; h < HPT; ++h) ph[h] = bload(rc, z1 + hcol[h]);
+      for (int h = 0; h < HPT; ++h) ph[h] = bload(rh, hcol[h]);
     }
-    float* buf = lds + (z & 1) * PL;
+    float* buf = lds + (z & 1) * PLB;
 #pragma unroll
-    for (int i = 0; i < RY; ++i) buf[lid[i]] = zw[i][R];
+    for (int i = 0; i < RY; ++i) buf[lid0 + i * RSTEP] = zw[i][(R + rot) % W];
 #pragma unroll
     for (int h = 0; h < HPT; ++h) buf[hlid[h]] = hv[h];
     __syncthreads();
 
-    const float stz = A.has_damp ? cload(A.stz, z) : 0.0f;
-    const int ip0 = A.inj.npts ? cload(A.inj.zptr, z) : 0, ip1 = A.inj.npts ? cload(A.inj.zptr, z + 1) : 0;
-    const int sp0 = A.smp.npts ? cload(A.smp.zptr, z) : 0, sp1 = A.smp.npts ? cload(A.smp.zptr, z + 1) : 0;
-    const uint32_t zo = zoff(z);
-    rsrc_t rh = make_rsrc(A.b, 0u), rg = rh;
+    const bool zown = z < zb;
+    const float stz = A.has_damp ? damp_term(z, n0, A.nbl, A.st_coef) : 0.0f;
+    const bool fz = zown && z >= A.inj_zlo && z < A.inj_zhi && cload(A.inj.zptr, z + 1) > cload(A.inj.zptr, z);
+    const bool sz = zown && z >= A.smp_zlo && z < A.smp_zhi && cload(A.smp.zptr, z + 1) > cload(A.smp.zptr, z);
+    const rsrc_t ro = plane(A.outA, z, za, zb, s0, PB);
+    rsrc_t rh = ro, rg = ro;
     if (MODE != MODE_FWD) {
-      rh = make_rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N + base, seg);
-      if (MODE == MODE_ADJ) rg = make_rsrc(A.grad + base, seg);
+      rh = plane(A.hist + (int64_t)(step + 1 - A.hist_base) * N, z, za, zb, s0, PB);
+      if (MODE == MODE_ADJ) rg = plane(A.grad, z, za, zb, s0, PB);
     }
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       float zm[R], zp[R], ym[R], yp[R], xm[R], xp[R];
-      const float* row = buf + lid[i];
+      const float* row = buf + lid0 + i * RSTEP;
 #pragma unroll
       for (int j = 1; j <= R; ++j) {
-        zm[j - 1] = zw[i][R - j];
-        zp[j - 1] = zw[i][R + j];
+        zm[j - 1] = zw[i][(R - j + rot) % W];
+        zp[j - 1] = zw[i][(R + j + rot) % W];
         xm[j - 1] = row[-j];
         xp[j - 1] = row[j];
-        if (HY) {
-          ym[j - 1] = row[-j * LDW];
-          yp[j - 1] = row[j * LDW];
+        if (HY) {   // rows held by this thread come from registers
+          ym[j - 1] = (i - j >= 0) ? zw[(i - j >= 0) ? i - j : 0][(R + rot) % W] : row[-j * LDW];
+          yp[j - 1] = (i + j < RY) ? zw[(i + j < RY) ? i + j : 0][(R + rot) % W] : row[j * LDW];
         }
       }
-      const float st = A.has_damp ? (stz + sty[i]) + stx[i] : 0.0f;
-      const float f = (ip1 > ip0) ? forcing_in(A, ip0, ip1, gy[i], gx[i], step) : 0.0f;
-      const float v = wave_point<R, HY>(A.C, zw[i][R], zm, zp, ym, yp, xm, xp, up[i], bb[i], st, f);
-      const uint32_t o = zo + col[i];
+      const float uc = zw[i][(R + rot) % W];
+      float f = 0.0f;
+      if (fz) {
+        const int ly = HY ? wv * RY + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
+        f = forcing_in(A, cload(A.inj.zptr, z), cload(A.inj.zptr, z + 1), gy0 + ly, gx0 + lx, step);
+      }
+      const float st = A.has_damp ? (stz + sty[i]) + stx[HY ? 0 : i] : 0.0f;
+      float v = wave_num<R, HY>(A.C, uc, zm, zp, ym, yp, xm, xp, up[i], bb[i], st, f, A.has_damp != 0, fz);
+      if (A.has_damp && wave_any(st != 0.0f)) v = wave_damp(v, st);
+      const uint32_t o = col[i];
       bstore(ro, o, v);
-      if (sp1 > sp0 && col[i] < kOOB) sample_in(A, sp0, sp1, gy[i], gx[i], step, v);
+      if (sz && o != kOOB) {
+        const int ly = HY ? wv * RY + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
+        sample_in(A, cload(A.smp.zptr, z), cload(A.smp.zptr, z + 1), gy0 + ly, gx0 + lx, step, v);
+      }
       if (MODE == MODE_HIST) {
         bstore(rh, o, v);
       } else if (MODE == MODE_ADJ) {
         const float u = bload(rh, o);
-        bstore(rg, o, image_step(bload(rg, o), u, st, v, zw[i][R], up[i]));
+        bstore(rg, o, image_step(bload(rg, o), u, st, v, uc, up[i]));
+      }
+    }
+  };
+  if constexpr (ROT) {
+    // iterations past the segment end store nothing (empty plane descriptors)
+    for (int it = 0; it < nit; it += W)
+      unroll_rot([&](auto r) { body(za + it + decltype(r)::value, std::integral_constant<int, decltype(r)::value + 1>{}); },
+                 std::make_integer_sequence<int, W>{});
+  } else {
+    for (int it = 0; it < nit; ++it) {
+      body(za + it, std::integral_constant<int, 1>{});
+      // rotate the ring by one slot so that the fixed rotation 1 stays valid
+#pragma unroll
+      for (int i = 0; i < RY; ++i) {
+        const float t0 = zw[i][0];
+#pragma unroll
+        for (int j = 0; j < W - 1; ++j) zw[i][j] = zw[i][j + 1];
+        zw[i][W - 1] = t0;
       }
     }
   }
@@ -248,16 +311,19 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
 template <int R, int T, int DIM, int MODE, int NW, int RY>
 __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
   constexpr bool HY = (DIM == 3);
+  constexpr int W = 2 * R + 1;
+  constexpr bool ROT = W <= kMaxUnrollW;
   constexpr int EY = HY ? NW * RY : 1;
   constexpr int EX = HY ? 64 : 64 * NW * RY;
   constexpr int RYH = HY ? R : 0;
   constexpr int LDW = EX + 2 * R;
-  constexpr int LDH = EY + 2 * RYH;
-  constexpr int PL = LDW * LDH;                                  // floats per LDS plane
-  constexpr int NBUF = tiled_nbuf(R, T, EY, EX, HY);           // double-buffer when it fits
-  extern __shared__ float lds[];                                 // NBUF * T planes
+  constexpr int PL = tiled_plane_floats(R, EY, EX, HY);
+  constexpr int NBUF = tiled_nbuf(R, T, EY, EX, HY);
+  constexpr int RSTEP = HY ? LDW : 64;
+  extern __shared__ float lds[];   // NBUF * T planes
 
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int H = A.skew * T;
   const int HYH = HY ? H : 0;
   const int CY = HY ? EY - 2 * H : 1;
@@ -266,60 +332,68 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
   const int gy0 = ty * CY - HYH, gx0 = tx * CX - H;
   const int za = blockIdx.y * A.zchunk;
   const int zb = min(za + A.zchunk, A.n0);
-  const int zlo = max(0, za - T * R - R), zhi = min(A.n0, zb + T * R + R);
-  const uint32_t PS = (uint32_t)A.s0 * 4u;
-  const uint32_t seg = (uint32_t)(zhi - zlo) * PS;
-  const int64_t base = (int64_t)zlo * A.s0;
-  const rsrc_t rc = make_rsrc(A.cur + base, seg);
-  const rsrc_t rp = make_rsrc(A.prev + base, seg);
-  const rsrc_t rb = make_rsrc(A.b + base, seg);
-  const rsrc_t ra = make_rsrc(A.outA + base, seg);
-  const rsrc_t rB = make_rsrc(A.outB ? A.outB + base : A.outA + base, A.outB ? seg : 0u);
-  auto zoff = [&](int z) -> uint32_t { return (z >= zlo && z < zhi) ? (uint32_t)(z - zlo) * PS : kOOB; };
+  const int n0 = A.n0;
+  const int64_t s0 = A.s0;
+  const uint32_t PB = (uint32_t)s0 * 4u;
 
   for (int e = threadIdx.x; e < NBUF * T * PL; e += 64 * NW) lds[e] = 0.0f;
 
-  uint32_t col[RY], ccol[RY];   // column offset (OOB outside the grid); same, OOB outside the core
-  int lid[RY], gy[RY], gx[RY];
-  float sty[RY], stx[RY];
-  bool inr[RY];
+  // Column offsets (kOOB outside the grid).  3D: a thread's rows are
+  // wave-uniform, so row validity, the core test along axis 1 and the damping
+  // terms along axes 0/1 are scalars; along axis 2 they are per lane.
+  uint32_t col[RY];
+  bool rcore[RY], xcore[HY ? 1 : RY];
+  float sty[RY], stx[HY ? 1 : RY];
+  const int lid0 = (HY ? wv * RY + RYH : 0) * LDW + (HY ? lane : wv * RY * 64 + lane) + R;
 #pragma unroll
   for (int i = 0; i < RY; ++i) {
     const int ly = HY ? wv * RY + i : 0;
     const int lx = HY ? lane : (wv * RY + i) * 64 + lane;
-    gy[i] = gy0 + ly;
-    gx[i] = gx0 + lx;
-    inr[i] = gy[i] >= 0 && gy[i] < A.n1 && gx[i] >= 0 && gx[i] < A.n2;
-    const bool core = inr[i] && lx >= H && lx < H + CX && (!HY || (ly >= HYH && ly < HYH + CY));
-    col[i] = inr[i] ? (uint32_t)(gy[i] * (int)A.s1 + gx[i]) * 4u : kOOB;
-    ccol[i] = core ? col[i] : kOOB;
-    lid[i] = (ly + RYH) * LDW + lx + R;
-    sty[i] = (A.has_damp && HY && inr[i]) ? A.sty[gy[i]] : 0.0f;
-    stx[i] = (A.has_damp && inr[i]) ? A.stx[gx[i]] : 0.0f;
+    const int gy = gy0 + ly, gx = gx0 + lx;
+    const bool yin = gy >= 0 && gy < A.n1, xin = gx >= 0 && gx < A.n2;
+    col[i] = (yin && xin) ? (uint32_t)(gy * (int)A.s1 + gx) * 4u : kOOB;
+    rcore[i] = !HY || (ly >= HYH && ly < HYH + CY);
+    sty[i] = (A.has_damp && HY) ? damp_term(gy, A.n1, A.nbl, A.st_coef) : 0.0f;
+    if (!HY || i == 0) {
+      xcore[HY ? 0 : i] = lx >= H && lx < H + CX;
+      stx[HY ? 0 : i] = A.has_damp ? damp_term(gx, A.n2, A.nbl, A.st_coef) : 0.0f;
+    }
   }
+  const int wrow0 = HY ? wv * RY : 0;   // first row of this wave (3D)
 
-  float win[T][RY][2 * R + 1];
+  float win[T][RY][W];
 #pragma unroll
   for (int k = 0; k < T; ++k)
 #pragma unroll
     for (int i = 0; i < RY; ++i)
 #pragma unroll
-      for (int j = 0; j <= 2 * R; ++j) win[k][i][j] = 0.0f;
+      for (int j = 0; j < W; ++j) win[k][i][j] = 0.0f;
 
-  const int zs = za - T * R;          // first plane loaded
-  const int ze = zb + T * R;          // one past the last iteration
-  float pc[RY], pp[RY], pb[T][RY];    // next iteration's loads
+  const int zs = za - T * R;   // first plane loaded
+  const int nit = zb - za + 2 * T * R;
+  float pc[RY], pp[RY], pb[T][RY];   // next iteration's loads
+  {
+    const rsrc_t rc = plane(A.cur, zs, 0, n0, s0, PB);
+    const rsrc_t rp = plane(A.prev, zs - R, 0, n0, s0, PB);
 #pragma unroll
-  for (int i = 0; i < RY; ++i) {
-    pc[i] = bload(rc, zoff(zs) + col[i]);
-    pp[i] = bload(rp, zoff(zs - R) + col[i]);
+    for (int i = 0; i < RY; ++i) {
+      pc[i] = bload(rc, col[i]);
+      pp[i] = bload(rp, col[i]);
+    }
 #pragma unroll
-    for (int k = 0; k < T; ++k) pb[k][i] = bload(rb, zoff(zs - (k + 1) * R) + col[i]);
+    for (int k = 0; k < T; ++k) {
+      const rsrc_t rb = plane(A.b, zs - (k + 1) * R, 0, n0, s0, PB);
+#pragma unroll
+      for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i]);
+    }
   }
   __syncthreads();
 
-  const int64_t N = (int64_t)A.n0 * A.s0;
-  for (int z0 = zs; z0 < ze; ++z0) {
+  const int64_t N = (int64_t)n0 * s0;
+  // One iteration; `rot` is the rotation after this iteration's pushes.
+  auto body = [&](int z0, auto rotc) {
+    constexpr int rot = decltype(rotc)::value;
+    __builtin_amdgcn_sched_barrier(0);   // keep unrolled copies from overlapping (register pressure)
     float cin[RY], pin[RY], bin[T][RY];
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
@@ -330,97 +404,120 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
     }
     {  // next iteration's loads first
       const int zn = z0 + 1;
-      const uint32_t oc = zoff(zn), op = zoff(zn - R);
+      const rsrc_t rc = plane(A.cur, zn, 0, n0, s0, PB);
+      const rsrc_t rp = plane(A.prev, zn - R, 0, n0, s0, PB);
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
-        pc[i] = bload(rc, oc + col[i]);
-        pp[i] = bload(rp, op + col[i]);
+        pc[i] = bload(rc, col[i]);
+        pp[i] = bload(rp, col[i]);
       }
 #pragma unroll
       for (int k = 0; k < T; ++k) {
-        const uint32_t ob = zoff(zn - (k + 1) * R);
+        const rsrc_t rb = plane(A.b, zn - (k + 1) * R, 0, n0, s0, PB);
 #pragma unroll
-        for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, ob + col[i]);
+        for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i]);
       }
     }
     // Stage the input plane of every stage in LDS: for stage k+1 that is level
-    // n+k at plane z0-(k+1)R, which sits at index R+1 of window k before this
-    // iteration's pushes.
+    // n+k at plane z0-(k+1)R, logical index R+1 of window k before this
+    // iteration's pushes (rotation rot-1), i.e. slot (R + rot) % W.
     float* buf = lds + ((NBUF == 2) ? (z0 & 1) : 0) * (T * PL);
 #pragma unroll
     for (int k = 0; k < T; ++k)
 #pragma unroll
-      for (int i = 0; i < RY; ++i) buf[k * PL + lid[i]] = win[k][i][R + 1];
+      for (int i = 0; i < RY; ++i) buf[k * PL + lid0 + i * RSTEP] = win[k][i][(R + rot) % W];
     __syncthreads();
     // push the freshly loaded plane z0 of level n into window 0
 #pragma unroll
-    for (int i = 0; i < RY; ++i) {
-#pragma unroll
-      for (int j = 0; j < 2 * R; ++j) win[0][i][j] = win[0][i][j + 1];
-      win[0][i][2 * R] = cin[i];
-    }
+    for (int i = 0; i < RY; ++i) win[0][i][(2 * R + rot) % W] = cin[i];
 #pragma unroll
     for (int k = 1; k <= T; ++k) {
       const int zk = z0 - k * R;
-      const bool zin = zk >= 0 && zk < A.n0;
+      const bool zin = zk >= 0 && zk < n0;
       const bool zown = zk >= za && zk < zb;
       const int step = stage_step(A, k);
       const float* pl = buf + (k - 1) * PL;
-      const float stz = (A.has_damp && zin) ? cload(A.stz, zk) : 0.0f;
-      const int ip0 = (A.inj.npts && zin) ? cload(A.inj.zptr, zk) : 0, ip1 = (A.inj.npts && zin) ? cload(A.inj.zptr, zk + 1) : 0;
-      const int sp0 = (A.smp.npts && zown) ? cload(A.smp.zptr, zk) : 0, sp1 = (A.smp.npts && zown) ? cload(A.smp.zptr, zk + 1) : 0;
-      const uint32_t zo = zoff(zk);
-      const uint32_t zown_o = zown ? zo : kOOB;
-      rsrc_t rh = make_rsrc(A.b, 0u), rg = rh;
+      const float stz = A.has_damp ? damp_term(zk, n0, A.nbl, A.st_coef) : 0.0f;
+      const bool fz = zk >= A.inj_zlo && zk < A.inj_zhi && cload(A.inj.zptr, zk + 1) > cload(A.inj.zptr, zk);
+      const bool sz = zown && zk >= A.smp_zlo && zk < A.smp_zhi && cload(A.smp.zptr, zk + 1) > cload(A.smp.zptr, zk);
+      const rsrc_t ra = plane(A.outA, zk, za, zb, s0, PB);
+      const rsrc_t rB = plane(A.outB ? A.outB : A.outA, zk, za, A.outB ? zb : za, s0, PB);
+      rsrc_t rh = ra, rg = ra;
       if (MODE != MODE_FWD) {
-        rh = make_rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N + base, seg);
-        if (MODE == MODE_ADJ) rg = make_rsrc(A.grad + base, seg);
+        rh = plane(A.hist + (int64_t)(step + 1 - A.hist_base) * N, zk, za, zb, s0, PB);
+        if (MODE == MODE_ADJ) rg = plane(A.grad, zk, za, zb, s0, PB);
       }
-      float res[RY];
+      // 3D: stage k is only needed on rows [k*skew, EY - k*skew) (uniform per wave)
+      const int vlo = HY ? k * A.skew : 0, vhi = HY ? EY - k * A.skew : 1;
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
-        float zm[R], zp[R], ym[R], yp[R], xm[R], xp[R];
-        const float* row = pl + lid[i];
+        float v = 0.0f;
+        const int ly = HY ? wrow0 + i : 0;   // 2D: every slot is on the single row
+        if (!HY || (ly >= vlo && ly < vhi)) {
+          float zm[R], zp[R], ym[R], yp[R], xm[R], xp[R];
+          const float* row = pl + lid0 + i * RSTEP;
 #pragma unroll
-        for (int j = 1; j <= R; ++j) {
-          zm[j - 1] = win[k - 1][i][R - j];
-          zp[j - 1] = win[k - 1][i][R + j];
-          xm[j - 1] = row[-j];
-          xp[j - 1] = row[j];
-          if (HY) {
-            ym[j - 1] = row[-j * LDW];
-            yp[j - 1] = row[j * LDW];
+          for (int j = 1; j <= R; ++j) {
+            zm[j - 1] = win[k - 1][i][(R - j + rot) % W];
+            zp[j - 1] = win[k - 1][i][(R + j + rot) % W];
+            xm[j - 1] = row[-j];
+            xp[j - 1] = row[j];
+            if (HY) {   // rows held by this thread come from registers
+              ym[j - 1] = (i - j >= 0) ? win[k - 1][(i - j >= 0) ? i - j : 0][(R + rot) % W] : row[-j * LDW];
+              yp[j - 1] = (i + j < RY) ? win[k - 1][(i + j < RY) ? i + j : 0][(R + rot) % W] : row[j * LDW];
+            }
+          }
+          const float uc = win[k - 1][i][(R + rot) % W];
+          const float up = (k == 1) ? pin[i] : win[(k >= 2) ? k - 2 : 0][i][rot % W];
+          float f = 0.0f;
+          if (fz) {
+            const int lx = HY ? lane : (wv * RY + i) * 64 + lane;
+            f = forcing_in(A, cload(A.inj.zptr, zk), cload(A.inj.zptr, zk + 1), gy0 + ly, gx0 + lx, step);
+          }
+          const float st = A.has_damp ? (stz + sty[i]) + stx[HY ? 0 : i] : 0.0f;
+          v = wave_num<R, HY>(A.C, uc, zm, zp, ym, yp, xm, xp, up, bin[k - 1][i], st, f, A.has_damp != 0, fz);
+          if (A.has_damp && wave_any(st != 0.0f)) v = wave_damp(v, st);
+          // in range only for core points (the plane descriptors cover owned planes only)
+          const uint32_t o = (rcore[i] && xcore[HY ? 0 : i]) ? col[i] : kOOB;
+          if (sz && o != kOOB) {
+            const int lx = HY ? lane : (wv * RY + i) * 64 + lane;
+            sample_in(A, cload(A.smp.zptr, zk), cload(A.smp.zptr, zk + 1), gy0 + ly, gx0 + lx, step, v);
+          }
+          if (MODE == MODE_HIST) {
+            bstore(rh, o, v);
+          } else if (MODE == MODE_ADJ) {
+            const float u = bload(rh, o);
+            bstore(rg, o, image_step(bload(rg, o), u, st, v, uc, up));
+          }
+          if (k == T) {
+            bstore(ra, o, v);
+            bstore(rB, o, uc);
           }
         }
-        const float up = (k == 1) ? pin[i] : win[(k >= 2) ? k - 2 : 0][i][0];
-        const float st = A.has_damp ? (stz + sty[i]) + stx[i] : 0.0f;
-        const float f = (ip1 > ip0) ? forcing_in(A, ip0, ip1, gy[i], gx[i], step) : 0.0f;
-        float v = wave_point<R, HY>(A.C, win[k - 1][i][R], zm, zp, ym, yp, xm, xp, up, bin[k - 1][i], st, f);
-        v = (inr[i] && zin) ? v : 0.0f;
-        res[i] = v;
-        const uint32_t o = zown_o + ccol[i];          // in range only for owned core points
-        if (sp1 > sp0 && o < kOOB) sample_in(A, sp0, sp1, gy[i], gx[i], step, v);
-        if (MODE == MODE_HIST) {
-          bstore(rh, o, v);
-        } else if (MODE == MODE_ADJ) {
-          const float u = bload(rh, o);
-          bstore(rg, o, image_step(bload(rg, o), u, st, v, win[k - 1][i][R], up));
-        }
-        if (k == T) {
-          bstore(ra, o, v);
-          bstore(rB, o, win[T - 1][i][R]);
-        }
-      }
-      if (k < T) {
-#pragma unroll
-        for (int i = 0; i < RY; ++i) {
-#pragma unroll
-          for (int j = 0; j < 2 * R; ++j) win[k][i][j] = win[k][i][j + 1];
-          win[k][i][2 * R] = res[i];
-        }
+        if (k < T) win[k][i][(2 * R + rot) % W] = v;
       }
     }
     if (NBUF == 1) __syncthreads();
+  };
+  if constexpr (ROT) {
+    // iterations past the segment end store nothing (empty plane descriptors)
+    for (int it = 0; it < nit; it += W)
+      unroll_rot([&](auto r) { body(zs + it + decltype(r)::value, std::integral_constant<int, decltype(r)::value + 1>{}); },
+                 std::make_integer_sequence<int, W>{});
+  } else {
+    for (int it = 0; it < nit; ++it) {
+      body(zs + it, std::integral_constant<int, 1>{});
+      // rotate every ring by one slot so that the fixed rotation 1 stays valid
+#pragma unroll
+      for (int k = 0; k < T; ++k)
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+          const float t0 = win[k][i][0];
+#pragma unroll
+          for (int j = 0; j < W - 1; ++j) win[k][i][j] = win[k][i][j + 1];
+          win[k][i][W - 1] = t0;
+        }
+    }
   }
 }
 

@@ -8,10 +8,10 @@ namespace wavett {
 enum : int { KIND_UNTILED = 0, KIND_TILED = 1 };
 
 // Thread-block shapes.  Untiled: core TY x TX.  Tiled: extended tile EY x EX.
-//   3D untiled      4 waves x 4 rows        -> 16 x 64 core
-//   3D tiled, s=1  16 waves x 4 rows        -> 64 x 64 extended tile (1024 threads)
-//   3D tiled, s=2   8 waves x 4 rows        -> 32 x 64 extended tile (512 threads)
-//   2D (both)       4 waves x 4 segments    -> 1 x 1024
+//   3D untiled        4 waves x 4 rows       -> 16 x 64 core (256 threads)
+//   3D tiled, shape 1 8 waves x 8 rows       -> 64 x 64 extended tile (512 threads)
+//   3D tiled, shape 2 8 waves x 4 rows       -> 32 x 64 extended tile (512 threads)
+//   2D (both)         4 waves x 4 segments   -> 1 x 1024 (256 threads)
 struct BlockShape { int nw, ry, ey, ex; };
 BlockShape block_shape(int kind, int dim, int shape);
 
@@ -22,18 +22,20 @@ int tiled_tmax(int R, int dim, int shape);
 hipError_t launch_sweep(int R, int kind, int T, int dim, int mode, int shape, const SweepArgs& A,
                         dim3 grid, size_t lds_bytes, hipStream_t s);
 
-// Per-radius entry points (one translation unit each).
-#define WAVE_DECL(RR) \
-  hipError_t launch_sweep_r##RR(int kind, int T, int dim, int mode, int shape, const SweepArgs& A, \
-                                dim3 grid, size_t lds_bytes, hipStream_t s);
+// Per-(radius, mode) entry points, one translation unit each.
+#define WAVE_DECL1(RR, MM) \
+  hipError_t launch_sweep_r##RR##_m##MM(int kind, int T, int dim, int shape, const SweepArgs& A, \
+                                        dim3 grid, size_t lds_bytes, hipStream_t s);
+#define WAVE_DECL(RR) WAVE_DECL1(RR, 0) WAVE_DECL1(RR, 1) WAVE_DECL1(RR, 2)
 WAVE_DECL(1) WAVE_DECL(2) WAVE_DECL(3) WAVE_DECL(4) WAVE_DECL(5) WAVE_DECL(6) WAVE_DECL(7) WAVE_DECL(8)
 #undef WAVE_DECL
+#undef WAVE_DECL1
 
 // Depth limits per (radius, dim, shape), shared by host planning and the
 // instantiation units.  Bounded by the register file: every fused level keeps
 // a (2R+1)-plane window per column.
-constexpr int kTmax3D_S1[9] = {0, 8, 5, 3, 3, 2, 2, 1, 1};
-constexpr int kTmax3D_S2[9] = {0, 8, 6, 4, 3, 2, 2, 1, 1};
-constexpr int kTmax2D[9] = {0, 8, 8, 6, 5, 4, 3, 3, 2};
+constexpr int kTmax3D_S1[9] = {0, 4, 4, 3, 2, 2, 2, 1, 1};
+constexpr int kTmax3D_S2[9] = {0, 6, 6, 4, 3, 2, 2, 2, 1};
+constexpr int kTmax2D[9] = {0, 4, 4, 4, 4, 2, 2, 2, 2};
 
 }  // namespace wavett

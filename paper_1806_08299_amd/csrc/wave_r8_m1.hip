@@ -1,0 +1,4 @@
+// Sweep kernels of stencil radius 8 (space order 16), mode 1 (0 forward, 1 forward storing history, 2 adjoint with imaging).
+#define WAVE_R 8
+#define WAVE_MODE 1
+#include "wave_inst.inc"

@@ -85,6 +85,7 @@ def lib():
             "wave_adjoint_grad": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, i32, P, sz]),
             "wave_batch": (i32, [P, i32, i32, P, P, P, P, P, P, P, P, i32, P, P]),
             "wave_autotune": (i32, [P, i32, i32, i32, P, sz, P]),
+            "wave_tiled_max_depth": (i32, [i32, i32, i32]),
             "wave_ai_naive": (dbl, [dbl, i32]),
             "wave_ai_tight": (dbl, [dbl, i32, i32, P, P, P, dbl]),
             "wave_flops_per_point": (dbl, [i32, i32, i32]),
@@ -194,6 +195,10 @@ def wave_autotune(ctx, trial_steps, repeats, max_T, scratch):
                              scratch.numel() * scratch.element_size(), ctypes.byref(best))
     _check(st, ctx)
     return best.value
+
+
+def wave_tiled_max_depth(space_order: int, ndim: int, tile_shape: int = 1) -> int:
+    return int(lib().wave_tiled_max_depth(space_order, ndim, tile_shape))
 
 
 def wave_ai_naive(ai_space: float, t_t: int) -> float:

@@ -45,16 +45,13 @@ def rel(a, b):
     return np.linalg.norm(np.ravel(a).astype(np.float64) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
 
 
-TMAX = {3: {1: [0, 8, 5, 3, 3, 2, 2, 1, 1], 2: [0, 8, 6, 4, 3, 2, 2, 1, 1]},
-        2: {0: [0, 8, 8, 6, 5, 4, 3, 3, 2]}}
-
-
 def _schedules(R, ndim):
     """Every (T, tile shape) built for radius R; the caller drops those the
     device cannot hold (WAVE_EUNSUPPORTED from set_schedule)."""
+    from paper_1806_08299_amd.wave import wave_tiled_max_depth
     out = []
-    for shape, tab in TMAX[ndim].items():
-        for T in range(1, tab[R] + 1):
+    for shape in ((1, 2) if ndim == 3 else (0,)):
+        for T in range(1, wave_tiled_max_depth(2 * R, ndim, shape) + 1):
             out.append((T, shape))
     return out
 
@@ -240,7 +237,7 @@ def test_error_paths():
     assert e.value.status == -3                       # WAVE_ECFL
     op = _op(w, time_tile=-1)
     with pytest.raises(WaveError) as e:
-        op.set_schedule(8, 0, 1, 0)                   # T beyond what is built for so8
+        op.set_schedule(7, 0, 1, 0)                   # T beyond what is built for so8
     assert e.value.status == -7
     from paper_1806_08299_amd.wave import wave_forward
     tiny = torch.empty(16, dtype=torch.uint8, device="cuda")
