@@ -42,6 +42,7 @@ struct wave_ctx {
     const void* scratch = nullptr;
     std::vector<double> src, rec;
   } ck;
+  SweepAux aux_host[4];   // sources of the per-call table copies
   std::string err;
 };
 
@@ -276,6 +277,23 @@ wave_status upload_points(wave_ctx* c, const PointTable& P, char*& cursor, DevPo
   return WAVE_OK;
 }
 
+// Device copy of the forcing/sampling tables of a window set (kept in ctx
+// storage until the next call so the asynchronous copy has a live source).
+wave_status upload_aux(wave_ctx* c, const DevPoints* inj, const float* inj_table, const DevPoints* smp,
+                       float* smp_out, SweepAux* dev, SweepAux& host) {
+  host = SweepAux{};
+  if (inj) {
+    host.inj = inj->set;
+    host.inj_table = inj_table;
+  }
+  if (smp && smp_out) {
+    host.smp = smp->set;
+    host.smp_out = smp_out;
+  }
+  HIP_TRY(c, hipMemcpyAsync(dev, &host, sizeof(SweepAux), hipMemcpyHostToDevice, c->stream));
+  return WAVE_OK;
+}
+
 dim3 grid1d(int64_t n) {
   int64_t b = (n + 255) / 256;
   return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536)));
@@ -339,6 +357,13 @@ wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p) {
   int zc = c->zchunks > 0 ? c->zchunks : auto_zchunks(c, base, kind, T);
   zc = (int)std::min<int64_t>(zc, c->n0);
   p.zchunk = (int)((c->n0 + zc - 1) / zc);
+  // A workgroup addresses its segment of planes (chunk plus pipeline halo)
+  // through one buffer descriptor per array, at most kSegMax bytes.
+  const int64_t plane_bytes = c->n1 * c->n2 * (int64_t)sizeof(float);
+  const int64_t halo = 2LL * ((kind == KIND_UNTILED ? 0 : T) + 1) * c->R;
+  const int64_t max_chunk = (int64_t)kSegMax / plane_bytes - halo;
+  if (max_chunk < 1) return fail(c, WAVE_EUNSUPPORTED, "grid plane too large for one buffer segment");
+  if (p.zchunk > max_chunk) p.zchunk = (int)max_chunk;
   p.zc = (int)((c->n0 + p.zchunk - 1) / p.zchunk);
   return WAVE_OK;
 }
@@ -395,6 +420,7 @@ struct Window {
   float* hist;
   int hist_base;
   float* grad;
+  const SweepAux* aux;   // device copy of the forcing/sampling tables
 };
 
 wave_status run_steps(wave_ctx* c, Waves& W, int step0, int steps, int dir, const Window& win) {
@@ -408,15 +434,12 @@ wave_status run_steps(wave_ctx* c, Waves& W, int step0, int steps, int dir, cons
     SweepArgs A = base_args(c);
     A.cur = W.C();
     A.prev = W.P();
+    A.aux = win.aux;
     if (win.inj && win.inj->set.npts > 0) {
-      A.inj = win.inj->set;
-      A.inj_table = win.inj_table;
       A.inj_zlo = win.inj->zlo;
       A.inj_zhi = win.inj->zhi;
     }
     if (win.smp && win.smp->set.npts > 0 && win.smp_out) {
-      A.smp = win.smp->set;
-      A.smp_out = win.smp_out;
       A.smp_zlo = win.smp->zlo;
       A.smp_zhi = win.smp->zhi;
     }
@@ -452,6 +475,7 @@ wave_status run_steps(wave_ctx* c, Waves& W, int step0, int steps, int dir, cons
 // ----------------------------------------------------------- scratch layout
 
 struct Layout {
+  size_t aux = 0;                    // SweepAux blocks
   size_t tab_src = 0, tab_rec = 0;   // point tables
   size_t inj = 0;                    // forcing table [nt][npts_src]
   size_t smp = 0;                    // sample buffer [nt][npts_rec]
@@ -467,6 +491,7 @@ Layout layout(const wave_ctx* c, int nt, int nsrc, int nrec, int K, int adjoint)
   Layout L;
   const int nd = c->dim;
   size_t o = 0;
+  L.aux = o; o += align_up(4 * sizeof(SweepAux));
   L.tab_src = o; o += table_bytes_bound(c->n0, nsrc, nd);
   L.tab_rec = o; o += table_bytes_bound(c->n0, nrec, nd);
   L.inj = o; o += align_up(sizeof(float) * (size_t)nt * ((size_t)nsrc << nd));
@@ -530,7 +555,9 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
     if ((s = fill(c, W.P(), c->N, 0.0f))) return s;
   }
   float* ck = K > 0 ? (float*)(scratch + L.ckpt) : nullptr;
-  Window win{&DS, table, PR.npts > 0 ? &DR : nullptr, samp, nullptr, 0, nullptr};
+  SweepAux* auxd = (SweepAux*)(scratch + L.aux);
+  if ((s = upload_aux(c, &DS, table, PR.npts > 0 ? &DR : nullptr, samp, auxd, c->aux_host[0]))) return s;
+  Window win{&DS, table, PR.npts > 0 ? &DR : nullptr, samp, nullptr, 0, nullptr, auxd};
   int n = 0;
   while (n < nt) {
     if (ck && n % K == 0) {
@@ -867,8 +894,13 @@ wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const doubl
   if ((s = fill(c, M.C(), c->N, 0.0f))) return s;
   if ((s = fill(c, M.P(), c->N, 0.0f))) return s;
   if ((s = fill(c, grad_m, c->N, 0.0f))) return s;
-  Window fw{&DS, table, nullptr, nullptr, hist, 0, nullptr};
-  Window bw{PR.npts > 0 ? &DR : nullptr, atab, (grad_q && PS.npts > 0) ? &DS : nullptr, asmp, hist, 0, grad_m};
+  SweepAux* auxd = (SweepAux*)(sc + L.aux);
+  const DevPoints* bw_inj = PR.npts > 0 ? &DR : nullptr;
+  const DevPoints* bw_smp = (grad_q && PS.npts > 0) ? &DS : nullptr;
+  if ((s = upload_aux(c, &DS, table, nullptr, nullptr, auxd + 1, c->aux_host[1]))) return s;
+  if ((s = upload_aux(c, bw_inj, atab, bw_smp, asmp, auxd + 2, c->aux_host[2]))) return s;
+  Window fw{&DS, table, nullptr, nullptr, hist, 0, nullptr, auxd + 1};
+  Window bw{bw_inj, atab, bw_smp, asmp, hist, 0, grad_m, auxd + 2};
   for (int seg = L.nseg - 1; seg >= 0; --seg) {
     const int c0 = seg * K, c1 = std::min(nt, c0 + K);
     U.cur = 0;

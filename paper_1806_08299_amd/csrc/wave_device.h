@@ -88,6 +88,15 @@ struct PointSet {
   int32_t npts;
 };
 
+// Tables of a call, in device memory: only the few planes holding points
+// read them, so they are kept out of the kernel's live scalar state.
+struct SweepAux {
+  PointSet inj;                // forcing points
+  const float* inj_table;      // [steps][inj.npts]
+  PointSet smp;                // sampled points
+  float* smp_out;              // [steps][smp.npts]
+};
+
 // Kernel modes.
 enum : int { MODE_FWD = 0, MODE_HIST = 1, MODE_ADJ = 2 };
 
@@ -106,11 +115,8 @@ struct SweepArgs {
   int32_t has_damp;            // 0: st == 0 everywhere
   int32_t nbl;
   float st_coef;               // sigma_max * dt / (2 nbl^2)
-  PointSet inj;                // forcing points
-  const float* inj_table;      // [steps][inj.npts]
+  const struct SweepAux* aux;  // forcing / sampling tables (device memory), read on the rare path only
   int32_t inj_zlo, inj_zhi;    // planes holding forcing points: [inj_zlo, inj_zhi)
-  PointSet smp;                // sampled points
-  float* smp_out;              // [steps][smp.npts] or null
   int32_t smp_zlo, smp_zhi;    // planes holding sampled points
   int32_t step0;               // step index produced by stage 1
   int32_t dir;                 // +1 forward, -1 adjoint: stage k produces step0 + dir (k-1)

@@ -32,14 +32,17 @@
 // registers; only the others are read from LDS.
 //
 // Memory access discipline.  Global traffic goes through raw buffer
-// instructions.  Each plane access builds its descriptor with scalar ops (base
-// at that plane, one plane of records, or zero records when the plane is
-// outside the grid or outside what the workgroup may store), so the per-lane
-// offset is just the precomputed column offset, and out-of-grid columns carry
-// an offset beyond any plane: the hardware returns 0 for loads (the zero
-// boundary values) and drops stores.  Every load is issued one plane ahead of
-// its use.  Because b = dt^2/m also reads as 0 outside the grid, the update
-// there evaluates to exactly +0 with no select.
+// instructions with one descriptor per array covering the segment of planes a
+// workgroup may touch (at most kSegMax bytes).  The plane offset is the
+// instruction's scalar offset and the column offset its vector offset; the
+// hardware range check covers their sum.  Out-of-grid columns carry kOOB, and
+// planes outside the grid (or, for stores, outside the planes a workgroup
+// owns) get the segment length as scalar offset, so every such access lands
+// past the descriptor without wrapping 32 bits: loads return 0 (the zero
+// boundary values) and stores are dropped, with no branches and no 64-bit
+// address arithmetic in the loop.  Every load is issued one plane ahead of its
+// use.  Because b = dt^2/m also reads as 0 outside the grid, the update there
+// evaluates to exactly +0 with no select.
 #pragma once
 #include <utility>
 
@@ -51,7 +54,8 @@ namespace wavett {
 
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 
-constexpr uint32_t kOOB = 0xFFFFFFF0u;   // column offset of an out-of-grid lane
+constexpr uint32_t kSegMax = 0x40000000u;   // largest segment a descriptor covers (host-enforced)
+constexpr uint32_t kOOB = 0x80000000u;      // column offset of an out-of-grid lane
 #ifndef WAVE_MAX_UNROLL_W
 #define WAVE_MAX_UNROLL_W 9
 #endif
@@ -60,18 +64,30 @@ constexpr int kMaxUnrollW = WAVE_MAX_UNROLL_W;   // unroll the z loop by the win
 __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
-// Descriptor of plane z of array p: empty unless lo <= z < hi.
-__device__ __forceinline__ rsrc_t plane(const float* p, int z, int lo, int hi, int64_t s0, uint32_t pbytes) {
-  const bool ok = z >= lo && z < hi;
-  return make_rsrc(p + (ok ? (int64_t)z * s0 : 0), ok ? pbytes : 0u);
-}
 // The b32 builtins move raw 32-bit words: reinterpret, never convert.
-__device__ __forceinline__ float bload(rsrc_t r, uint32_t off) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+// voff: per-lane column offset; soff: wave-uniform plane offset.
+__device__ __forceinline__ float bload(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-__device__ __forceinline__ void bstore(rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+__device__ __forceinline__ void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
 }
+
+// A workgroup's segment of planes [lo, hi) of every array.
+struct Seg {
+  int lo, hi;
+  uint32_t pb;    // bytes per plane
+  uint32_t len;   // (hi - lo) * pb
+  int64_t base;   // lo * plane elements
+  // scalar offset of plane z: in range only for lo <= z < hi (and a <= z < b)
+  __device__ __forceinline__ uint32_t off(int z) const {
+    return (z >= lo && z < hi) ? (uint32_t)(z - lo) * pb : len;
+  }
+  __device__ __forceinline__ uint32_t off(int z, int a, int b) const {
+    return (z >= a && z < b && z >= lo && z < hi) ? (uint32_t)(z - lo) * pb : len;
+  }
+  __device__ __forceinline__ rsrc_t rsrc(const float* p) const { return make_rsrc(p + base, len); }
+};
 
 // The point tables are read-only for the whole launch and indexed by uniform
 // values, so they are read through the constant address space: scalar loads
@@ -81,18 +97,44 @@ __device__ __forceinline__ V cload(const V* p, int64_t i) {
   return ((const __attribute__((address_space(4))) V*)p)[i];
 }
 
-__device__ __forceinline__ float forcing_in(const SweepArgs& A, int p0, int p1, int y, int x, int step) {
+// A copy of a pointer the optimiser cannot see through, so that loads behind
+// it stay on the rare path instead of being hoisted into live registers.
+template <typename P>
+__device__ __forceinline__ P opaque(P p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// Points of plane z (CSR over the streamed axis).
+__device__ __forceinline__ void plane_points(const PointSet& ps, int z, int& p0, int& p1) {
+  p0 = cload(ps.zptr, z);
+  p1 = cload(ps.zptr, z + 1);
+}
+
+// Forcing value at (z, y, x) for `step` (0 where the point is not forced).
+__device__ __forceinline__ float forcing_at(const SweepArgs& A, int z, int y, int x, int step) {
+  const SweepAux* X = opaque(A.aux);
+  const PointSet ps{cload(&X->inj.zptr, 0), cload(&X->inj.y, 0), cload(&X->inj.x, 0), cload(&X->inj.npts, 0)};
+  const float* tab = cload(&X->inj_table, 0);
+  int p0, p1;
+  plane_points(ps, z, p0, p1);
   float f = 0.0f;
   for (int p = p0; p < p1; ++p) {
-    const float v = cload(A.inj_table, (int64_t)step * A.inj.npts + p);
-    if (cload(A.inj.y, p) == y && cload(A.inj.x, p) == x) f = v;
+    const float v = cload(tab, (int64_t)step * ps.npts + p);
+    if (cload(ps.y, p) == y && cload(ps.x, p) == x) f = v;
   }
   return f;
 }
 
-__device__ __forceinline__ void sample_in(const SweepArgs& A, int p0, int p1, int y, int x, int step, float v) {
+// Record v at (z, y, x) for `step` if that point is sampled.
+__device__ __forceinline__ void sample_at(const SweepArgs& A, int z, int y, int x, int step, float v) {
+  const SweepAux* X = opaque(A.aux);
+  const PointSet ps{cload(&X->smp.zptr, 0), cload(&X->smp.y, 0), cload(&X->smp.x, 0), cload(&X->smp.npts, 0)};
+  float* out = cload(&X->smp_out, 0);
+  int p0, p1;
+  plane_points(ps, z, p0, p1);
   for (int p = p0; p < p1; ++p)
-    if (cload(A.smp.y, p) == y && cload(A.smp.x, p) == x) A.smp_out[(int64_t)step * A.smp.npts + p] = v;
+    if (cload(ps.y, p) == y && cload(ps.x, p) == x) out[(int64_t)step * ps.npts + p] = v;
 }
 
 // Whole-wave "any lane" test (uniform result).
@@ -132,13 +174,18 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
   const int za = blockIdx.y * A.zchunk;
   const int zb = min(za + A.zchunk, A.n0);
   const int n0 = A.n0;
-  const int64_t s0 = A.s0;
-  const uint32_t PB = (uint32_t)s0 * 4u;
+  Seg sg;
+  sg.lo = max(0, za - R);
+  sg.hi = min(n0, zb + R);
+  sg.pb = (uint32_t)A.s0 * 4u;
+  sg.len = (uint32_t)(sg.hi - sg.lo) * sg.pb;
+  sg.base = (int64_t)sg.lo * A.s0;
+  const rsrc_t rc = sg.rsrc(A.cur), rp = sg.rsrc(A.prev), rb = sg.rsrc(A.b), ro = sg.rsrc(A.outA);
 
   // 3D: the rows of a thread are wave-uniform, so their damping terms are
   // scalars; the axis-2 term is per lane.  2D: slots differ along axis 2.
   uint32_t col[RY];
-  float sty[RY], stx[HY ? 1 : RY];
+  float stx[HY ? 1 : RY];
   const int lid0 = (HY ? wv * RY + RYH : 0) * LDW + (HY ? lane : wv * RY * 64 + lane) + R;
 #pragma unroll
   for (int i = 0; i < RY; ++i) {
@@ -147,7 +194,6 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
     const int gy = gy0 + ly, gx = gx0 + lx;
     const bool in = gy < A.n1 && gx < A.n2;
     col[i] = in ? (uint32_t)(gy * (int)A.s1 + gx) * 4u : kOOB;
-    sty[i] = (A.has_damp && HY) ? damp_term(gy, A.n1, A.nbl, A.st_coef) : 0.0f;
     if (!HY || i == 0) stx[HY ? 0 : i] = A.has_damp ? damp_term(gx, A.n2, A.nbl, A.st_coef) : 0.0f;
   }
   uint32_t hcol[HPT];
@@ -182,27 +228,27 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
   {
 #pragma unroll
     for (int j = 1; j <= 2 * R; ++j) {   // planes za-R .. za+R-1: logical 0..2R-1 at rotation 1
-      const rsrc_t r = plane(A.cur, za - R - 1 + j, 0, n0, s0, PB);
+      const uint32_t so = sg.off(za - R - 1 + j);
 #pragma unroll
-      for (int i = 0; i < RY; ++i) zw[i][j % W] = bload(r, col[i]);
+      for (int i = 0; i < RY; ++i) zw[i][j % W] = bload(rc, col[i], so);
     }
-    const rsrc_t rc = plane(A.cur, za + R, 0, n0, s0, PB);
-    const rsrc_t rp = plane(A.prev, za, 0, n0, s0, PB);
-    const rsrc_t rb = plane(A.b, za, 0, n0, s0, PB);
-    const rsrc_t rh = plane(A.cur, za, 0, n0, s0, PB);
+    const uint32_t sc = sg.off(za + R), s1 = sg.off(za);
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       zw[i][0] = 0.0f;
-      pc[i] = bload(rc, col[i]);
-      pp[i] = bload(rp, col[i]);
-      pb[i] = bload(rb, col[i]);
+      pc[i] = bload(rc, col[i], sc);
+      pp[i] = bload(rp, col[i], s1);
+      pb[i] = bload(rb, col[i], s1);
     }
 #pragma unroll
-    for (int h = 0; h < HPT; ++h) ph[h] = bload(rh, hcol[h]);
+    for (int h = 0; h < HPT; ++h) ph[h] = bload(rc, hcol[h], s1);
   }
 
   const int step = A.step0;
-  const int64_t N = (int64_t)n0 * s0;
+  const int64_t N = (int64_t)n0 * A.s0;
+  // history / gradient: one time level per launch
+  const rsrc_t rh = (MODE != MODE_FWD) ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ro;
+  const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ro;
   const int nit = zb - za;
   // One plane; `rot` is the rotation after this iteration's push.
   auto body = [&](int z, auto rotc) {
@@ -218,18 +264,15 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
 #pragma unroll
     for (int h = 0; h < HPT; ++h) hv[h] = ph[h];
     {  // issue the next plane's loads before touching this plane's data
-      const rsrc_t rc = plane(A.cur, z + 1 + R, 0, n0, s0, PB);
-      const rsrc_t rp = plane(A.prev, z + 1, 0, n0, s0, PB);
-      const rsrc_t rb = plane(A.b, z + 1, 0, n0, s0, PB);
-      const rsrc_t rh = plane(A.cur, z + 1, 0, n0, s0, PB);
+      const uint32_t sc = sg.off(z + 1 + R), s1 = sg.off(z + 1);
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
-        pc[i] = bload(rc, col[i]);
-        pp[i] = bload(rp, col[i]);
-        pb[i] = bload(rb, col[i]);
+        pc[i] = bload(rc, col[i], sc);
+        pp[i] = bload(rp, col[i], s1);
+        pb[i] = bload(rb, col[i], s1);
       }
 #pragma unroll
-      for (int h = 0; h < HPT; ++h) ph[h] = bload(rh, hcol[h]);
+      for (int h = 0; h < HPT; ++h) ph[h] = bload(rc, hcol[h], s1);
     }
     float* buf = lds + (z & 1) * PLB;
 #pragma unroll
@@ -240,50 +283,77 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
 
     const bool zown = z < zb;
     const float stz = A.has_damp ? damp_term(z, n0, A.nbl, A.st_coef) : 0.0f;
-    const bool fz = zown && z >= A.inj_zlo && z < A.inj_zhi && cload(A.inj.zptr, z + 1) > cload(A.inj.zptr, z);
-    const bool sz = zown && z >= A.smp_zlo && z < A.smp_zhi && cload(A.smp.zptr, z + 1) > cload(A.smp.zptr, z);
-    const rsrc_t ro = plane(A.outA, z, za, zb, s0, PB);
-    rsrc_t rh = ro, rg = ro;
-    if (MODE != MODE_FWD) {
-      rh = plane(A.hist + (int64_t)(step + 1 - A.hist_base) * N, z, za, zb, s0, PB);
-      if (MODE == MODE_ADJ) rg = plane(A.grad, z, za, zb, s0, PB);
+    const bool fz = zown && z >= A.inj_zlo && z < A.inj_zhi;
+    const bool sz = zown && z >= A.smp_zlo && z < A.smp_zhi;
+    const uint32_t so = sg.off(z, za, zb);   // stores: owned planes only
+    // Wave-uniform variants keep every row of a plane in one straight-line
+    // block: damping only where some lane of the wave is inside the layer,
+    // forcing/sampling only on the planes that hold such points.
+    bool dmp = false;
+    if (A.has_damp) {
+      bool rows_damped = false;
+#pragma unroll
+      for (int i = 0; i < RY; ++i)
+        rows_damped |= HY && damp_term(gy0 + wv * RY + i, A.n1, A.nbl, A.st_coef) != 0.0f;
+      bool lane_damped = stz != 0.0f || rows_damped;
+#pragma unroll
+      for (int i = 0; i < (HY ? 1 : RY); ++i) lane_damped |= stx[i] != 0.0f;
+      dmp = wave_any(lane_damped);
     }
+    auto rows = [&](auto dm, auto ev) {
+      constexpr bool DM = decltype(dm)::value, EV = decltype(ev)::value;
+      float v[RY], st[RY];
 #pragma unroll
-    for (int i = 0; i < RY; ++i) {
-      float zm[R], zp[R], ym[R], yp[R], xm[R], xp[R];
-      const float* row = buf + lid0 + i * RSTEP;
+      for (int i = 0; i < RY; ++i) {
+        float zm[R], zp[R], ym[R], yp[R], xm[R], xp[R];
+        const float* row = buf + lid0 + i * RSTEP;
 #pragma unroll
-      for (int j = 1; j <= R; ++j) {
-        zm[j - 1] = zw[i][(R - j + rot) % W];
-        zp[j - 1] = zw[i][(R + j + rot) % W];
-        xm[j - 1] = row[-j];
-        xp[j - 1] = row[j];
-        if (HY) {   // rows held by this thread come from registers
-          ym[j - 1] = (i - j >= 0) ? zw[(i - j >= 0) ? i - j : 0][(R + rot) % W] : row[-j * LDW];
-          yp[j - 1] = (i + j < RY) ? zw[(i + j < RY) ? i + j : 0][(R + rot) % W] : row[j * LDW];
+        for (int j = 1; j <= R; ++j) {
+          zm[j - 1] = zw[i][(R - j + rot) % W];
+          zp[j - 1] = zw[i][(R + j + rot) % W];
+          xm[j - 1] = row[-j];
+          xp[j - 1] = row[j];
+          if (HY) {   // rows held by this thread come from registers
+            ym[j - 1] = (i - j >= 0) ? zw[(i - j >= 0) ? i - j : 0][(R + rot) % W] : row[-j * LDW];
+            yp[j - 1] = (i + j < RY) ? zw[(i + j < RY) ? i + j : 0][(R + rot) % W] : row[j * LDW];
+          }
+        }
+        float f = 0.0f;
+        if (EV && fz) {
+          const int ly = HY ? wv * RY + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
+          f = forcing_at(A, z, gy0 + ly, gx0 + lx, step);
+        }
+        st[i] = 0.0f;
+        if (DM) {
+          const float sty = HY ? damp_term(gy0 + wv * RY + i, A.n1, A.nbl, A.st_coef) : 0.0f;
+          st[i] = (stz + sty) + stx[HY ? 0 : i];
+        }
+        v[i] = wave_num<R, HY>(A.C, zw[i][(R + rot) % W], zm, zp, ym, yp, xm, xp, up[i], bb[i], st[i], f, DM,
+                               EV && fz);
+        if (DM) v[i] = wave_damp(v[i], st[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < RY; ++i) {
+        const uint32_t o = col[i];
+        bstore(ro, o, so, v[i]);
+        if (EV && sz && o != kOOB) {
+          const int ly = HY ? wv * RY + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
+          sample_at(A, z, gy0 + ly, gx0 + lx, step, v[i]);
+        }
+        if (MODE == MODE_HIST) {
+          bstore(rh, o, so, v[i]);
+        } else if (MODE == MODE_ADJ) {
+          const float u = bload(rh, o, so);
+          bstore(rg, o, so, image_step(bload(rg, o, so), u, st[i], v[i], zw[i][(R + rot) % W], up[i]));
         }
       }
-      const float uc = zw[i][(R + rot) % W];
-      float f = 0.0f;
-      if (fz) {
-        const int ly = HY ? wv * RY + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
-        f = forcing_in(A, cload(A.inj.zptr, z), cload(A.inj.zptr, z + 1), gy0 + ly, gx0 + lx, step);
-      }
-      const float st = A.has_damp ? (stz + sty[i]) + stx[HY ? 0 : i] : 0.0f;
-      float v = wave_num<R, HY>(A.C, uc, zm, zp, ym, yp, xm, xp, up[i], bb[i], st, f, A.has_damp != 0, fz);
-      if (A.has_damp && wave_any(st != 0.0f)) v = wave_damp(v, st);
-      const uint32_t o = col[i];
-      bstore(ro, o, v);
-      if (sz && o != kOOB) {
-        const int ly = HY ? wv * RY + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
-        sample_in(A, cload(A.smp.zptr, z), cload(A.smp.zptr, z + 1), gy0 + ly, gx0 + lx, step, v);
-      }
-      if (MODE == MODE_HIST) {
-        bstore(rh, o, v);
-      } else if (MODE == MODE_ADJ) {
-        const float u = bload(rh, o);
-        bstore(rg, o, image_step(bload(rg, o), u, st, v, uc, up[i]));
-      }
+    };
+    using TT = std::true_type;
+    using FF = std::false_type;
+    if (fz || sz) {
+      if (dmp) rows(TT{}, TT{}); else rows(FF{}, TT{});
+    } else {
+      if (dmp) rows(TT{}, FF{}); else rows(FF{}, FF{});
     }
   };
   if constexpr (ROT) {
@@ -333,8 +403,14 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
   const int za = blockIdx.y * A.zchunk;
   const int zb = min(za + A.zchunk, A.n0);
   const int n0 = A.n0;
-  const int64_t s0 = A.s0;
-  const uint32_t PB = (uint32_t)s0 * 4u;
+  Seg sg;
+  sg.lo = max(0, za - (T + 1) * R);
+  sg.hi = min(n0, zb + (T + 1) * R);
+  sg.pb = (uint32_t)A.s0 * 4u;
+  sg.len = (uint32_t)(sg.hi - sg.lo) * sg.pb;
+  sg.base = (int64_t)sg.lo * A.s0;
+  const rsrc_t rc = sg.rsrc(A.cur), rp = sg.rsrc(A.prev), rb = sg.rsrc(A.b), ra = sg.rsrc(A.outA);
+  const rsrc_t rB = A.outB ? sg.rsrc(A.outB) : make_rsrc(A.outA, 0u);
 
   for (int e = threadIdx.x; e < NBUF * T * PL; e += 64 * NW) lds[e] = 0.0f;
 
@@ -342,8 +418,8 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
   // wave-uniform, so row validity, the core test along axis 1 and the damping
   // terms along axes 0/1 are scalars; along axis 2 they are per lane.
   uint32_t col[RY];
-  bool rcore[RY], xcore[HY ? 1 : RY];
-  float sty[RY], stx[HY ? 1 : RY];
+  bool xcore[HY ? 1 : RY];
+  float stx[HY ? 1 : RY];
   const int lid0 = (HY ? wv * RY + RYH : 0) * LDW + (HY ? lane : wv * RY * 64 + lane) + R;
 #pragma unroll
   for (int i = 0; i < RY; ++i) {
@@ -352,8 +428,6 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
     const int gy = gy0 + ly, gx = gx0 + lx;
     const bool yin = gy >= 0 && gy < A.n1, xin = gx >= 0 && gx < A.n2;
     col[i] = (yin && xin) ? (uint32_t)(gy * (int)A.s1 + gx) * 4u : kOOB;
-    rcore[i] = !HY || (ly >= HYH && ly < HYH + CY);
-    sty[i] = (A.has_damp && HY) ? damp_term(gy, A.n1, A.nbl, A.st_coef) : 0.0f;
     if (!HY || i == 0) {
       xcore[HY ? 0 : i] = lx >= H && lx < H + CX;
       stx[HY ? 0 : i] = A.has_damp ? damp_term(gx, A.n2, A.nbl, A.st_coef) : 0.0f;
@@ -373,23 +447,22 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
   const int nit = zb - za + 2 * T * R;
   float pc[RY], pp[RY], pb[T][RY];   // next iteration's loads
   {
-    const rsrc_t rc = plane(A.cur, zs, 0, n0, s0, PB);
-    const rsrc_t rp = plane(A.prev, zs - R, 0, n0, s0, PB);
+    const uint32_t sc = sg.off(zs), sp = sg.off(zs - R);
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
-      pc[i] = bload(rc, col[i]);
-      pp[i] = bload(rp, col[i]);
+      pc[i] = bload(rc, col[i], sc);
+      pp[i] = bload(rp, col[i], sp);
     }
 #pragma unroll
     for (int k = 0; k < T; ++k) {
-      const rsrc_t rb = plane(A.b, zs - (k + 1) * R, 0, n0, s0, PB);
+      const uint32_t sb = sg.off(zs - (k + 1) * R);
 #pragma unroll
-      for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i]);
+      for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i], sb);
     }
   }
   __syncthreads();
 
-  const int64_t N = (int64_t)n0 * s0;
+  const int64_t N = (int64_t)n0 * A.s0;
   // One iteration; `rot` is the rotation after this iteration's pushes.
   auto body = [&](int z0, auto rotc) {
     constexpr int rot = decltype(rotc)::value;
@@ -404,18 +477,17 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
     }
     {  // next iteration's loads first
       const int zn = z0 + 1;
-      const rsrc_t rc = plane(A.cur, zn, 0, n0, s0, PB);
-      const rsrc_t rp = plane(A.prev, zn - R, 0, n0, s0, PB);
+      const uint32_t sc = sg.off(zn), sp = sg.off(zn - R);
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
-        pc[i] = bload(rc, col[i]);
-        pp[i] = bload(rp, col[i]);
+        pc[i] = bload(rc, col[i], sc);
+        pp[i] = bload(rp, col[i], sp);
       }
 #pragma unroll
       for (int k = 0; k < T; ++k) {
-        const rsrc_t rb = plane(A.b, zn - (k + 1) * R, 0, n0, s0, PB);
+        const uint32_t sb = sg.off(zn - (k + 1) * R);
 #pragma unroll
-        for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i]);
+        for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i], sb);
       }
     }
     // Stage the input plane of every stage in LDS: for stage k+1 that is level
@@ -438,22 +510,29 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
       const int step = stage_step(A, k);
       const float* pl = buf + (k - 1) * PL;
       const float stz = A.has_damp ? damp_term(zk, n0, A.nbl, A.st_coef) : 0.0f;
-      const bool fz = zk >= A.inj_zlo && zk < A.inj_zhi && cload(A.inj.zptr, zk + 1) > cload(A.inj.zptr, zk);
-      const bool sz = zown && zk >= A.smp_zlo && zk < A.smp_zhi && cload(A.smp.zptr, zk + 1) > cload(A.smp.zptr, zk);
-      const rsrc_t ra = plane(A.outA, zk, za, zb, s0, PB);
-      const rsrc_t rB = plane(A.outB ? A.outB : A.outA, zk, za, A.outB ? zb : za, s0, PB);
-      rsrc_t rh = ra, rg = ra;
-      if (MODE != MODE_FWD) {
-        rh = plane(A.hist + (int64_t)(step + 1 - A.hist_base) * N, zk, za, zb, s0, PB);
-        if (MODE == MODE_ADJ) rg = plane(A.grad, zk, za, zb, s0, PB);
-      }
-      // 3D: stage k is only needed on rows [k*skew, EY - k*skew) (uniform per wave)
-      const int vlo = HY ? k * A.skew : 0, vhi = HY ? EY - k * A.skew : 1;
+      const bool fz = zk >= A.inj_zlo && zk < A.inj_zhi;
+      const bool sz = zown && zk >= A.smp_zlo && zk < A.smp_zhi;
+      const uint32_t so = sg.off(zk, za, zb);   // stores: owned planes only
+      const rsrc_t rh = (MODE != MODE_FWD) ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
+      const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ra;
+      bool dmp = false;
+      if (A.has_damp) {
+        bool rows_damped = false;
 #pragma unroll
-      for (int i = 0; i < RY; ++i) {
-        float v = 0.0f;
-        const int ly = HY ? wrow0 + i : 0;   // 2D: every slot is on the single row
-        if (!HY || (ly >= vlo && ly < vhi)) {
+        for (int i = 0; i < RY; ++i)
+          rows_damped |= HY && damp_term(gy0 + wrow0 + i, A.n1, A.nbl, A.st_coef) != 0.0f;
+        bool lane_damped = stz != 0.0f || rows_damped;
+#pragma unroll
+        for (int i = 0; i < (HY ? 1 : RY); ++i) lane_damped |= stx[i] != 0.0f;
+        dmp = wave_any(lane_damped);
+      }
+      // Wave-uniform variants keep every row of a stage in one straight-line
+      // block (see the untiled kernel).
+      auto rows = [&](auto dm, auto ev) {
+        constexpr bool DM = decltype(dm)::value, EV = decltype(ev)::value;
+        float v[RY], st[RY], upv[RY];
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
           float zm[R], zp[R], ym[R], yp[R], xm[R], xp[R];
           const float* row = pl + lid0 + i * RSTEP;
 #pragma unroll
@@ -467,34 +546,53 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
               yp[j - 1] = (i + j < RY) ? win[k - 1][(i + j < RY) ? i + j : 0][(R + rot) % W] : row[j * LDW];
             }
           }
-          const float uc = win[k - 1][i][(R + rot) % W];
-          const float up = (k == 1) ? pin[i] : win[(k >= 2) ? k - 2 : 0][i][rot % W];
+          upv[i] = (k == 1) ? pin[i] : win[(k >= 2) ? k - 2 : 0][i][rot % W];
           float f = 0.0f;
-          if (fz) {
-            const int lx = HY ? lane : (wv * RY + i) * 64 + lane;
-            f = forcing_in(A, cload(A.inj.zptr, zk), cload(A.inj.zptr, zk + 1), gy0 + ly, gx0 + lx, step);
+          if (EV && fz) {
+            const int ly = HY ? wrow0 + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
+            f = forcing_at(A, zk, gy0 + ly, gx0 + lx, step);
           }
-          const float st = A.has_damp ? (stz + sty[i]) + stx[HY ? 0 : i] : 0.0f;
-          v = wave_num<R, HY>(A.C, uc, zm, zp, ym, yp, xm, xp, up, bin[k - 1][i], st, f, A.has_damp != 0, fz);
-          if (A.has_damp && wave_any(st != 0.0f)) v = wave_damp(v, st);
-          // in range only for core points (the plane descriptors cover owned planes only)
-          const uint32_t o = (rcore[i] && xcore[HY ? 0 : i]) ? col[i] : kOOB;
-          if (sz && o != kOOB) {
+          st[i] = 0.0f;
+          if (DM) {
+            const float sty = HY ? damp_term(gy0 + wrow0 + i, A.n1, A.nbl, A.st_coef) : 0.0f;
+            st[i] = (stz + sty) + stx[HY ? 0 : i];
+          }
+          v[i] = wave_num<R, HY>(A.C, win[k - 1][i][(R + rot) % W], zm, zp, ym, yp, xm, xp, upv[i],
+                                 bin[k - 1][i], st[i], f, DM, EV && fz);
+          if (DM) v[i] = wave_damp(v[i], st[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+          // in range only for core points of owned planes
+          const int ly = HY ? wrow0 + i : 0;
+          const bool rcore = !HY || (ly >= HYH && ly < HYH + CY);
+          const uint32_t o = (rcore && xcore[HY ? 0 : i]) ? col[i] : kOOB;
+          if (EV && sz && o != kOOB) {
             const int lx = HY ? lane : (wv * RY + i) * 64 + lane;
-            sample_in(A, cload(A.smp.zptr, zk), cload(A.smp.zptr, zk + 1), gy0 + ly, gx0 + lx, step, v);
+            sample_at(A, zk, gy0 + ly, gx0 + lx, step, v[i]);
           }
           if (MODE == MODE_HIST) {
-            bstore(rh, o, v);
+            bstore(rh, o, so, v[i]);
           } else if (MODE == MODE_ADJ) {
-            const float u = bload(rh, o);
-            bstore(rg, o, image_step(bload(rg, o), u, st, v, uc, up));
+            const float u = bload(rh, o, so);
+            bstore(rg, o, so, image_step(bload(rg, o, so), u, st[i], v[i], win[k - 1][i][(R + rot) % W], upv[i]));
           }
           if (k == T) {
-            bstore(ra, o, v);
-            bstore(rB, o, uc);
+            bstore(ra, o, so, v[i]);
+            bstore(rB, o, so, win[k - 1][i][(R + rot) % W]);
           }
         }
-        if (k < T) win[k][i][(2 * R + rot) % W] = v;
+        if (k < T) {
+#pragma unroll
+          for (int i = 0; i < RY; ++i) win[k < T ? k : 0][i][(2 * R + rot) % W] = v[i];
+        }
+      };
+      using TT = std::true_type;
+      using FF = std::false_type;
+      if (fz || sz) {
+        if (dmp) rows(TT{}, TT{}); else rows(FF{}, TT{});
+      } else {
+        if (dmp) rows(TT{}, FF{}); else rows(FF{}, FF{});
       }
     }
     if (NBUF == 1) __syncthreads();
