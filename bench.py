@@ -2,17 +2,23 @@
 """Throughput of the time-tiled acoustic-wave sweep on one MI355X.
 
 One "step" is one pass of the hot path over one synthetic batch: the full
-forward modelling of the 512^3 (+40-point absorbing layer = 592^3) space-order-8
-layered-model problem for 1000 time steps (source injection, receiver
-sampling, time-tiled sweep), with the inputs resident in HBM.  Reported:
+forward modelling of the 512^3 (+40-point absorbing layer = 592^3)
+space-order-8 layered-model problem for 1000 time steps (source injection,
+receiver sampling, the sweep), with every input resident in HBM.  Reported
+on one JSON line (progress goes to stderr):
 
-* value: grid-point updates per second of that step with the tuned
-  time-tiled schedule (Gpts/s = 592^3 * 1000 / wall);
-* untiled: the same step with the single-step (untiled) sweep, and the ratio;
-* adjoint_grad: the 256^3 (+40) so8 gradient problem (forward with
-  checkpoints every 50 steps, tiled recompute, time-reversed adjoint with the
-  imaging condition) for 2000 steps, in Gpts/s of forward time steps;
-* roofline: the dominant kernel (time-tiled forward sweep) against HBM;
+* value: grid-point updates per second of that step with the autotuned
+  schedule (time-tile depth T, tile shape, axis-0 segments; the untiled sweep
+  is one of the candidates), Gpts/s = 592^3 * 1000 * K / time of K steps;
+* untiled: the same step with the single-step sweep (its segment count tuned
+  the same way), and the ratio of the two;
+* adjoint_grad: the 256^3 (+40) space-order-8 gradient problem (forward with
+  checkpoints every 50 steps, recompute of each segment, time-reversed
+  adjoint with the imaging condition) for 2000 steps, tiled and untiled;
+* roofline: the dominant kernel of the step against HBM bandwidth, with the
+  HBM traffic read from hardware counters when a matching record exists;
+* ai: the arithmetic intensity measured from those counters beside the
+  naive and tight estimators of the time-tiling intensity model;
 * cpu_baseline: the FP64 oracle on the host cores on a bounded sample.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
@@ -20,6 +26,8 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -31,27 +39,91 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+L2_FLOATS = 4 * 2 ** 20 // 4          # 4 MiB L2 per XCD
+MALL_FLOATS = 256 * 2 ** 20 // 4      # 256 MiB last-level (Infinity) cache
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_forward(op, w, wav, steps, warmup, stream):
+def kernel_sources_sha() -> str:
+    """Digest of the HIP sources and build script: a counter record is only
+    used while the kernels it measured are unchanged."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1806_08299_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "paper_1806_08299_amd", "build.py"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(workload: str, sched) -> dict | None:
+    """Counter record (profiles/hbm_traffic.txt) for this workload, schedule
+    and kernel sources, or None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    sha = kernel_sources_sha()
+    T, _, shape, zc = sched
+    for line in open(path):
+        if not line.startswith("record "):
+            continue
+        kv = dict(f.split("=", 1) for f in line.split()[1:])
+        if (kv.get("workload") == workload and int(kv["T"]) == T and int(kv["shape"]) == shape
+                and int(kv["zchunks"]) == zc and kv.get("sources") == sha):
+            return kv
+    return None
+
+
+def run_steps(op, w, wav, steps, stream):
+    """K forward steps between two device synchronisations; returns seconds
+    (HIP events on the sweep's stream) and the host wall time."""
     import torch
-    for _ in range(warmup):
-        op.forward(w.nt, w.src_xyz, wav, w.rec_xyz)
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    times = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
     for _ in range(steps):
-        e0.record(stream)
         op.forward(w.nt, w.src_xyz, wav, w.rec_xyz)
-        e1.record(stream)
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1) * 1e-3)
-    return times
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3, time.perf_counter() - t0
+
+
+def tune_untiled(op, trial_steps=40, repeats=2):
+    """Best axis-0 segment count for the untiled sweep (short trials)."""
+    import torch
+    best = (1e30, 0)
+    for zc in (0, 1, 2, 4, 8, 16, 32):
+        op.set_schedule(-1, 0, 0, zc)
+        op.forward(trial_steps)
+        torch.cuda.synchronize()
+        t = 1e30
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            op.forward(trial_steps)
+            torch.cuda.synchronize()
+            t = min(t, time.perf_counter() - t0)
+        best = min(best, (t, zc))
+    op.set_schedule(-1, 0, 0, best[1])
+    return best[1]
+
+
+def autotune(op, trial_steps=40):
+    from paper_1806_08299_amd.wave import wave_autotune, wave_scratch_bytes
+    sc = op.scratch(wave_scratch_bytes(op.ctx, trial_steps, 0, 0, 0, 0))
+    return wave_autotune(op.ctx, trial_steps, 2, 8, sc)
+
+
+def kernel_name(sched, so) -> str:
+    T, _, shape, _ = sched
+    if T < 0:
+        return "k_untiled R=%d (single-step sweep)" % (so // 2)
+    return "k_tiled R=%d T=%d tile_shape=%d" % (so // 2, T, shape)
 
 
 def cpu_baseline(w, budget_s=20.0):
@@ -69,9 +141,72 @@ def cpu_baseline(w, budget_s=20.0):
     t0 = time.perf_counter()
     oracle.forward(g, m, steps, w.src_xyz, w.wavelet[:steps].astype(np.float64), w.rec_xyz)
     dt = time.perf_counter() - t0
-    return {"value": w.npts * steps / dt / 1e9, "unit": "Gpts/s", "cores": threads, "kind": "oracle",
-            "sample": "%s: first %d of %d time steps on the full %s grid (FP64, OpenMP over points), "
+    return {"value": round(w.npts * steps / dt / 1e9, 4), "unit": "Gpts/s", "cores": threads, "kind": "oracle",
+            "sample": "%s: first %d of %d time steps on the full %s grid (FP64, OpenMP over axis 0), "
                       "%.1f s" % (w.name, steps, w.nt, "x".join(map(str, w.shape)), dt)}
+
+
+def gradient_bench(args, dev, stream):
+    """Forward with checkpoints + recompute/adjoint/imaging on the 256^3 so8
+    gradient problem, with the autotuned and with the untiled schedule."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import WaveOp
+    from paper_1806_08299_amd.wave import wave_bytes_per_point
+    n4, nt4 = (96, 200) if args.quick else (256, 2000)
+    w4 = wi.gradient_256(nt=nt4, n=n4)
+    tr, init = w4["true"], w4["init"]
+    K = w4["ckpt_every"]
+    opt = WaveOp(tr.shape, tr.spacing, tr.dt, tr.so, torch.from_numpy(tr.m).to(dev), nbl=tr.nbl,
+                 sigma_max=tr.sigma_max, time_tile=-1)
+    dobs, _ = opt.forward(tr.nt, tr.src_xyz, torch.from_numpy(tr.wavelet).to(dev), tr.rec_xyz)
+    del opt
+    op = WaveOp(init.shape, init.spacing, init.dt, init.so, torch.from_numpy(init.m).to(dev), nbl=init.nbl,
+                sigma_max=init.sigma_max, time_tile=-1)
+    wv = torch.from_numpy(init.wavelet).to(dev)
+    autotune(op)
+    tuned = op.schedule()
+    out = {"workload": "%s, model %s, nt=%d, checkpoints every %d"
+                       % (init.name, "x".join(map(str, init.shape)), init.nt, K), "unit": "Gpts/s"}
+
+    def one(sched):
+        op.set_schedule(*sched)
+        best = None
+        for _ in range(2):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            torch.cuda.synchronize()
+            e0.record(stream)
+            rec, _ = op.forward(init.nt, init.src_xyz, wv, init.rec_xyz, ckpt_every=K, adjoint_scratch=True)
+            resid = rec - dobs
+            e1.record(stream)
+            gm, _ = op.adjoint_grad(init.nt, init.src_xyz, wv, init.rec_xyz, resid, K, reuse=True)
+            e2.record(stream)
+            torch.cuda.synchronize()
+            t = (e0.elapsed_time(e1) * 1e-3, e1.elapsed_time(e2) * 1e-3)
+            if best is None or sum(t) < sum(best):
+                best = t
+        return best, gm
+
+    (tf, ta), gm = one(tuned)
+    out.update({"schedule": dict(zip(("T", "skew", "tile_shape", "zchunks"), tuned)),
+                "value": round(init.npts * init.nt / (tf + ta) / 1e9, 2),
+                "forward_with_checkpoints_s": round(tf, 4), "recompute_plus_adjoint_s": round(ta, 4),
+                "grad_finite": bool(torch.isfinite(gm).all().item())})
+    # adjoint launch: recompute (history) + adjoint per segment; the adjoint
+    # kernel's algorithmic bytes per point-update
+    T = tuned[0]
+    out["adjoint_bytes_per_point_update"] = wave_bytes_per_point(T, 2)
+    out["history_bytes_per_point_update"] = wave_bytes_per_point(T, 1)
+    log("gradient %s: fwd %.3f s + recompute/adjoint %.3f s" % (tuned, tf, ta))
+    if not args.no_untiled:
+        (uf, ua), _ = one((-1, 0, 0, tuned[3] if tuned[0] < 0 else 0))
+        out["untiled"] = {"value": round(init.npts * init.nt / (uf + ua) / 1e9, 2),
+                          "forward_with_checkpoints_s": round(uf, 4), "recompute_plus_adjoint_s": round(ua, 4)}
+        out["speedup_vs_untiled"] = round((uf + ua) / (tf + ta), 3)
+        log("gradient untiled: fwd %.3f s + recompute/adjoint %.3f s" % (uf, ua))
+    del op
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -81,23 +216,26 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512, help="physical grid edge of the forward workload")
     ap.add_argument("--nt", type=int, default=1000)
-    ap.add_argument("--T", type=int, default=0, help="time-tile depth (0: autotune)")
-    ap.add_argument("--shape", type=int, default=0)
+    ap.add_argument("--T", type=int, default=0, help="time-tile depth (0: autotune, -1: untiled)")
+    ap.add_argument("--shape", type=int, default=1)
+    ap.add_argument("--zchunks", type=int, default=0)
+    ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for the traffic counters)")
     ap.add_argument("--quick", action="store_true", help="small sizes for a functional check")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the sweep has no multi-GPU path in this library "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
     import waveinputs as wi
     from paper_1806_08299_amd import WaveOp
-    from paper_1806_08299_amd.wave import (wave_autotune, wave_bytes_per_point, wave_flops_per_point,
-                                           wave_scratch_bytes)
+    from paper_1806_08299_amd.wave import wave_ai_naive, wave_ai_tight, wave_bytes_per_point, wave_flops_per_point
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -105,86 +243,90 @@ def main():
     if args.quick:
         args.n, args.nt = 128, 100
 
-    # ---------------------------------------------------------------- forward, tuned tiled schedule
+    if args.copy_calibration:
+        a = torch.empty(2 ** 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 3 copies of 1 GiB")
+
+    # ---------------------------------------------------------------- forward, tuned schedule
     t0 = time.time()
-    w = wi.c2(nt=args.nt, n=args.n)
+    w = wi.layered_512(nt=args.nt, n=args.n)
     log("workload %s shape %s nt %d (%.1f s to generate)" % (w.name, w.shape, w.nt, time.time() - t0))
     m = torch.from_numpy(w.m).to(dev)
     wav = torch.from_numpy(w.wavelet).to(dev)
     op = WaveOp(w.shape, w.spacing, w.dt, w.so, m, nbl=w.nbl, sigma_max=w.sigma_max, time_tile=-1)
-    if args.T > 0:
-        op.set_schedule(args.T, 0, args.shape, 0)
+    if args.T != 0:
+        op.set_schedule(args.T, 0, args.shape, args.zchunks)
     else:
-        sc = op.scratch(wave_scratch_bytes(op.ctx, 40, 0, 0, 0, 0))
-        best = wave_autotune(op.ctx, 40, 2, 8, sc)
+        best = autotune(op)
         log("autotune -> schedule %s, %.3f ms/step" % (op.schedule(), best * 1e3))
-    T, skew, shape, zch = op.schedule()
-    times = timed_forward(op, w, wav, args.steps, args.warmup, stream)
-    t_step = min(times)
+    sched = op.schedule()
+    T = sched[0]
+    for _ in range(args.warmup):
+        op.forward(w.nt, w.src_xyz, wav, w.rec_xyz)
+    elapsed, wall = run_steps(op, w, wav, args.steps, stream)
+    t_step = elapsed / args.steps
     value = w.npts * w.nt / t_step / 1e9
-    log("tiled T=%d shape=%d: %.3f s/step -> %.1f Gpts/s" % (T, shape, t_step, value))
+    log("schedule %s: %.4f s/step (wall %.4f) -> %.1f Gpts/s" % (sched, t_step, wall / args.steps, value))
 
     # ---------------------------------------------------------------- untiled reference sweep
-    op.set_schedule(-1, 0, 0, 0)
-    ut = timed_forward(op, w, wav, max(1, args.steps // 2), 1, stream)
-    untiled = w.npts * w.nt / min(ut) / 1e9
-    log("untiled: %.3f s/step -> %.1f Gpts/s" % (min(ut), untiled))
-    op.set_schedule(T, skew, shape, zch)
+    untiled = None
+    if not args.no_untiled:
+        zu = tune_untiled(op)
+        op.forward(w.nt, w.src_xyz, wav, w.rec_xyz)
+        ue, _ = run_steps(op, w, wav, max(1, args.steps), stream)
+        ut = ue / max(1, args.steps)
+        untiled = {"value": round(w.npts * w.nt / ut / 1e9, 2), "ms_per_step": round(ut * 1e3, 3), "zchunks": zu}
+        log("untiled (zchunks %d): %.4f s/step -> %.1f Gpts/s" % (zu, ut, untiled["value"]))
+        op.set_schedule(*sched)
 
-    # ---------------------------------------------------------------- roofline of the tiled kernel
-    # launches per step: ceil(nt / T) windows of the tiled kernel; the step's
-    # other kernels (forcing table, two fills, receiver reduction) are < 0.1 %.
-    launches = -(-w.nt // T) if T > 0 else w.nt
+    # ---------------------------------------------------------------- roofline of the dominant kernel
+    # One step = ceil(nt / T) launches of the sweep kernel plus four small
+    # kernels (forcing table, two fills, receiver reduction; < 0.1 % of the
+    # step), so the kernel's average launch time is bounded by step / launches.
+    Tn = max(T, 1)
+    launches = -(-w.nt // Tn)
     t_launch = t_step / launches
-    bpp = wave_bytes_per_point(T, 0)                     # algorithmic bytes per point-update
-    pts_per_launch = w.npts * (T if T > 0 else 1)
-    achieved = bpp * pts_per_launch / t_launch / 1e9
+    bpp = wave_bytes_per_point(T, 0)
+    alg_bytes = bpp * w.npts * Tn                   # per launch (full window)
+    achieved = alg_bytes / t_launch / 1e9
+    flops_pt = wave_flops_per_point(3, w.so, 0)
+    rec = traffic_record(w.name, sched)
+    traffic = None
+    if rec is not None:
+        f = float(rec["fetch_kib"]) * float(rec["copy_bytes"]) / float(rec["copy_fetch_kib"])
+        wr = float(rec["write_kib"]) * float(rec["copy_bytes"]) / float(rec["copy_write_kib"])
+        traffic = round(f + wr)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_tiled R=4 T=%d" % T, "bytes_per_point_update": bpp,
-                "flops_per_point_update": wave_flops_per_point(3, w.so, 0),
-                "avg_launch_ms": round(t_launch * 1e3, 4)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": kernel_name(sched, w.so), "algorithmic_bytes_per_launch": alg_bytes,
+                "bytes_per_point_update": bpp, "points_per_launch": w.npts * Tn,
+                "avg_launch_ms": round(t_launch * 1e3, 4), "launches_per_step": launches}
 
-    del op
+    # ---------------------------------------------------------------- arithmetic intensity
+    # AI of the untiled sweep: useful flops per compulsory byte; the estimators
+    # take it times T (naive) and shrink it by re-loaded tile faces (tight),
+    # with the cache read as one XCD's L2 or as the shared last-level cache.
+    ai_s = flops_pt / 16.0
+    ai = {"flops_per_point_update": flops_pt, "untiled_ai": round(ai_s, 4),
+          "naive": round(wave_ai_naive(ai_s, Tn), 4)}
+    if T >= 1:
+        from paper_1806_08299_amd.wave import block_extent
+        ey, ex = block_extent(3, sched[2])
+        for nm, om in (("tight_l2", L2_FLOATS), ("tight_mall", MALL_FLOATS)):
+            ai[nm] = round(wave_ai_tight(ai_s, Tn, w.shape, [w.so // 2] * 3, [w.shape[0], ey, ex], om), 4)
+    if traffic:
+        ai["measured"] = round(flops_pt * w.npts * Tn / traffic, 4)
+    ai["compulsory"] = round(flops_pt / bpp, 4)
+    del op, m, wav
     torch.cuda.empty_cache()
 
-    # ---------------------------------------------------------------- adjoint gradient
-    adj = None
-    if not args.no_adjoint:
-        n4, nt4 = (96, 200) if args.quick else (256, 2000)
-        w4 = wi.c4(nt=nt4, n=n4)
-        tr, init = w4["true"], w4["init"]
-        K = w4["ckpt_every"]
-        opt = WaveOp(tr.shape, tr.spacing, tr.dt, tr.so, torch.from_numpy(tr.m).to(dev), nbl=tr.nbl,
-                     sigma_max=tr.sigma_max, time_tile=T if T > 0 else -1)
-        dobs, _ = opt.forward(tr.nt, tr.src_xyz, torch.from_numpy(tr.wavelet).to(dev), tr.rec_xyz)
-        del opt
-        op4 = WaveOp(init.shape, init.spacing, init.dt, init.so, torch.from_numpy(init.m).to(dev), nbl=init.nbl,
-                     sigma_max=init.sigma_max, time_tile=T if T > 0 else -1)
-        wv4 = torch.from_numpy(init.wavelet).to(dev)
-        gtimes = []
-        for it in range(2):
-            torch.cuda.synchronize()
-            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-            e0.record(stream)
-            rec, _ = op4.forward(init.nt, init.src_xyz, wv4, init.rec_xyz, ckpt_every=K, adjoint_scratch=True)
-            resid = rec - dobs
-            e1.record(stream)
-            gm, _ = op4.adjoint_grad(init.nt, init.src_xyz, wv4, init.rec_xyz, resid, K, reuse=True)
-            e2.record(stream)
-            e2.synchronize()
-            gtimes.append((e0.elapsed_time(e1) * 1e-3, e1.elapsed_time(e2) * 1e-3))
-        tf, ta = min(g[0] for g in gtimes), min(g[1] for g in gtimes)
-        adj = {"workload": "c4_256cube_so8 (+40 layer = %s), nt=%d, checkpoints every %d"
-                           % ("x".join(map(str, init.shape)), init.nt, K),
-               "value": round(init.npts * init.nt / (tf + ta) / 1e9, 2), "unit": "Gpts/s",
-               "forward_with_checkpoints_s": round(tf, 4), "recompute_plus_adjoint_s": round(ta, 4),
-               "adjoint_only_gpts": round(init.npts * init.nt / ta / 1e9, 2),
-               "grad_finite": bool(torch.isfinite(gm).all().item())}
-        log("gradient: fwd %.3f s + adjoint %.3f s" % (tf, ta))
-        del op4
-        torch.cuda.empty_cache()
-
+    adj = None if args.no_adjoint else gradient_bench(args, dev, stream)
     cpu = None if args.no_cpu else cpu_baseline(w)
 
     line = {
@@ -193,12 +335,13 @@ def main():
         "ms_per_step": round(t_step * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "shape": list(w.shape), "physical": [args.n] * 3, "nbl": w.nbl,
-                   "space_order": w.so, "nt": w.nt, "schedule": {"T": T, "skew": skew, "tile_shape": shape,
-                                                                  "zchunks": zch}},
-        "untiled": {"value": round(untiled, 2), "ms_per_step": round(min(ut) * 1e3, 3)},
-        "speedup_vs_untiled": round(value / untiled, 3),
+                   "space_order": w.so, "nt": w.nt,
+                   "schedule": dict(zip(("T", "skew", "tile_shape", "zchunks"), sched))},
+        "untiled": untiled,
+        "speedup_vs_untiled": round(value / untiled["value"], 3) if untiled else None,
         "adjoint_grad": adj,
         "roofline": roofline,
+        "ai": ai,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -157,9 +157,11 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
                        int32_t ckpt_every, void* const* scratch_dev, const size_t* scratch_bytes);
 
 /* Autotune the schedule (T, skew, tile shape, zchunks) on this context's
- * model by timing short trial sweeps; keeps the fastest (minimum of
- * `repeats` trials per candidate).  Synchronises; needs scratch for
- * `trial_steps` forward steps without sources.  max_T bounds the search. */
+ * model by timing short trial sweeps (minimum of `repeats` trials per
+ * candidate): first every depth T <= max_T and tile shape at the default
+ * number of axis-0 segments, then 1..32 segments for the three fastest.
+ * Keeps the fastest.  Synchronises; needs scratch for `trial_steps` forward
+ * steps without sources. */
 wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
                           void* scratch_dev, size_t scratch_bytes, double* best_seconds_per_step);
 
@@ -182,9 +184,17 @@ double wave_ai_tight(double ai_space, int32_t t_t, int32_t ndim, const double* D
  * file: every fused level keeps a (so+1)-plane window per column.  Host-only. */
 int32_t wave_tiled_max_depth(int32_t space_order, int32_t ndim, int32_t tile_shape);
 
+/* Extended (y, x) tile of one workgroup of the time-tiled sweep for
+ * tile_shape (ignored in 2D, where y is 1): the columns it loads, of which
+ * the inner (ey - 2 skew T) x (ex - 2 skew T) are written.  Host-only.
+ * Returns WAVE_EINVAL for an unknown shape or ndim. */
+wave_status wave_tile_extent(int32_t ndim, int32_t tile_shape, int32_t* ey, int32_t* ex);
+
 /* Flops per point-update of the sweep (adds + multiplies, FMA = 2) for order
  * so in ndim dimensions, and compulsory HBM bytes per point-update of the
- * schedule (T = -1 untiled; damping computed from indices). Host-only. */
+ * schedule (T = -1 untiled; damping computed from indices) for mode 0
+ * (forward), 1 (forward storing the history, +4 B) or 2 (adjoint reading the
+ * history and updating the gradient at every stage, +12 B). Host-only. */
 double wave_flops_per_point(int32_t ndim, int32_t space_order, int32_t damped);
 double wave_bytes_per_point(int32_t time_tile, int32_t mode);
 

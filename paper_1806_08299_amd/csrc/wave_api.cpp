@@ -391,8 +391,10 @@ wave_status launch_window(wave_ctx* c, const Plan& p, SweepArgs A) {
   A.core_y = p.core_y;
   A.core_x = p.core_x;
   A.tiles_x = p.tiles_x;
+  A.ntiles = p.tiles_x * p.tiles_y;
+  A.nblocks = A.ntiles * p.zc;
   A.zchunk = p.zchunk;
-  dim3 grid((unsigned)((int64_t)p.tiles_x * p.tiles_y), (unsigned)p.zc);
+  dim3 grid((unsigned)A.nblocks);
   int mode = MODE_FWD;
   if (A.grad) mode = MODE_ADJ;
   else if (A.hist) mode = MODE_HIST;
@@ -952,26 +954,43 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
-  double best_t = 1e300;
-  Cand bc{oT, os, osh, oz};
-  for (const Cand& k : cands) {
-    if (apply_schedule(c, k.T, k.skew, k.shape ? k.shape : 1, k.zc) != WAVE_OK) continue;
+  auto time_one = [&](const Cand& k) -> double {
+    if (apply_schedule(c, k.T, k.skew, k.shape ? k.shape : 1, k.zc) != WAVE_OK) return 1e300;
     double tmin = 1e300;
-    bool ok = true;
-    for (int r = 0; r < repeats + 1 && ok; ++r) {
+    for (int r = 0; r < repeats + 1; ++r) {
       hipEventRecord(e0, c->stream);
       if (forward_core(c, trial_steps, 0, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, (char*)scratch,
                        L) != WAVE_OK)
-        ok = false;
+        return 1e300;
       hipEventRecord(e1, c->stream);
-      if (hipEventSynchronize(e1) != hipSuccess) ok = false;
+      if (hipEventSynchronize(e1) != hipSuccess) return 1e300;
       float ms = 0;
       hipEventElapsedTime(&ms, e0, e1);
       if (r > 0) tmin = std::min(tmin, (double)ms * 1e-3);   // first run is a warm-up
     }
-    if (ok && tmin < best_t) {
-      best_t = tmin;
-      bc = k;
+    return tmin;
+  };
+  // Phase 1: depth and tile shape at the default number of axis-0 segments.
+  std::vector<std::pair<double, Cand>> timed;
+  for (const Cand& k : cands) timed.push_back({time_one(k), k});
+  std::stable_sort(timed.begin(), timed.end(),
+                   [](const std::pair<double, Cand>& x, const std::pair<double, Cand>& y) { return x.first < y.first; });
+  double best_t = timed.empty() ? 1e300 : timed[0].first;
+  Cand bc = timed.empty() ? Cand{oT, os, osh, oz} : timed[0].second;
+  // Phase 2: the number of axis-0 segments (grid size against per-workgroup
+  // pipeline fill) for the three fastest schedules.
+  const int zcs[6] = {1, 2, 4, 8, 16, 32};
+  for (size_t t = 0; t < std::min<size_t>(3, timed.size()); ++t) {
+    if (timed[t].first >= 1e300) break;
+    for (int z : zcs) {
+      if (z > c->n0) break;
+      Cand k = timed[t].second;
+      k.zc = z;
+      const double tz = time_one(k);
+      if (tz < best_t) {
+        best_t = tz;
+        bc = k;
+      }
     }
   }
   hipEventDestroy(e0);
@@ -1022,6 +1041,15 @@ double wave_ai_tight(double ai_space, int32_t t_t, int32_t n, const double* D, c
   return wave_ai_naive(ai_space, t_t) / (1.0 + frac);
 }
 
+wave_status wave_tile_extent(int32_t ndim, int32_t tile_shape, int32_t* ey, int32_t* ex) {
+  if ((ndim != 2 && ndim != 3) || (ndim == 3 && (tile_shape < 0 || tile_shape > 2)) || !ey || !ex)
+    return WAVE_EINVAL;
+  const BlockShape bs = block_shape(KIND_TILED, ndim, tile_shape == 0 ? 1 : tile_shape);
+  *ey = bs.ey;
+  *ex = bs.ex;
+  return WAVE_OK;
+}
+
 double wave_flops_per_point(int32_t ndim, int32_t so, int32_t damped) {
   // centre product, per axis per pair one add + one FMA, forcing add, (1 - st),
   // 2u, two FMAs; inside the layer one add, the reciprocal and one multiply.
@@ -1032,7 +1060,8 @@ double wave_flops_per_point(int32_t ndim, int32_t so, int32_t damped) {
 double wave_bytes_per_point(int32_t T, int32_t mode) {
   // compulsory traffic per point-update: read u^n, u^{n-1}, b once per launch,
   // write one level (in place, T <= 1) or two levels (ping-pong, T >= 2);
-  // history +4 B (write or read); imaging gradient +8 B (read-modify-write).
+  // history +4 B (write or read); imaging gradient +8 B (read-modify-write
+  // at every stage of the window).
   const double Tt = T < 1 ? 1.0 : (double)T;
   double base = (T <= 1) ? 16.0 : 20.0 / Tt;
   if (mode == 1) base += 4.0;

@@ -126,8 +126,10 @@ struct SweepArgs {
   // tiling
   int32_t skew;                // halo per fused step on the tiled axes
   int32_t core_y, core_x;      // core tile extents
-  int32_t tiles_x;             // number of tiles along x (blockIdx.x = ty*tiles_x + tx)
-  int32_t zchunk;              // streamed-axis segment length per block (blockIdx.y)
+  int32_t tiles_x;             // tiles along x; tile index = ty * tiles_x + tx
+  int32_t ntiles;              // tiles per axis-0 segment
+  int32_t nblocks;             // ntiles * number of axis-0 segments (1D grid)
+  int32_t zchunk;              // streamed-axis segment length per block
 };
 
 // LDS planes of the tiled kernel: each is (EX + 2R) x (EY + 2R_y) floats; one
@@ -145,6 +147,15 @@ constexpr size_t tiled_lds_bytes(int R, int T, int EY, int EX, bool HY) {
 __device__ __forceinline__ float damp_term(int i, int n, int nbl, float coef) {
   const int d = max(max(nbl - i, i - (n - 1 - nbl)), 0);
   return coef * (float)(d * d);
+}
+
+// Work item of this workgroup: tiles vary fastest, then axis-0 segments, so
+// the workgroups resident at any moment cover one compact front of the grid
+// (neighbouring tiles re-read each other's halo columns from the shared
+// last-level cache while they are still there).
+__device__ __forceinline__ void work_item(const SweepArgs& A, int& tile, int& chunk) {
+  chunk = blockIdx.x / A.ntiles;
+  tile = blockIdx.x % A.ntiles;
 }
 
 // Step of stage k (1-based) of a launch.

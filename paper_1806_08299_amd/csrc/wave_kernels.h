@@ -169,9 +169,11 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  const int ty = blockIdx.x / A.tiles_x, tx = blockIdx.x % A.tiles_x;
+  int tile, chunk;
+  work_item(A, tile, chunk);
+  const int ty = tile / A.tiles_x, tx = tile % A.tiles_x;
   const int gy0 = ty * TY, gx0 = tx * TX;
-  const int za = blockIdx.y * A.zchunk;
+  const int za = chunk * A.zchunk;
   const int zb = min(za + A.zchunk, A.n0);
   const int n0 = A.n0;
   Seg sg;
@@ -398,9 +400,11 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
   const int HYH = HY ? H : 0;
   const int CY = HY ? EY - 2 * H : 1;
   const int CX = EX - 2 * H;
-  const int ty = blockIdx.x / A.tiles_x, tx = blockIdx.x % A.tiles_x;
+  int tile, chunk;
+  work_item(A, tile, chunk);
+  const int ty = tile / A.tiles_x, tx = tile % A.tiles_x;
   const int gy0 = ty * CY - HYH, gx0 = tx * CX - H;
-  const int za = blockIdx.y * A.zchunk;
+  const int za = chunk * A.zchunk;
   const int zb = min(za + A.zchunk, A.n0);
   const int n0 = A.n0;
   Seg sg;

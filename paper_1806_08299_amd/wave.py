@@ -86,6 +86,7 @@ def lib():
             "wave_batch": (i32, [P, i32, i32, P, P, P, P, P, P, P, P, i32, P, P]),
             "wave_autotune": (i32, [P, i32, i32, i32, P, sz, P]),
             "wave_tiled_max_depth": (i32, [i32, i32, i32]),
+            "wave_tile_extent": (i32, [i32, i32, P, P]),
             "wave_ai_naive": (dbl, [dbl, i32]),
             "wave_ai_tight": (dbl, [dbl, i32, i32, P, P, P, dbl]),
             "wave_flops_per_point": (dbl, [i32, i32, i32]),
@@ -199,6 +200,13 @@ def wave_autotune(ctx, trial_steps, repeats, max_T, scratch):
 
 def wave_tiled_max_depth(space_order: int, ndim: int, tile_shape: int = 1) -> int:
     return int(lib().wave_tiled_max_depth(space_order, ndim, tile_shape))
+
+
+def block_extent(ndim: int, tile_shape: int = 1):
+    """(ey, ex) columns loaded by one workgroup of the time-tiled sweep."""
+    ey, ex = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().wave_tile_extent(ndim, tile_shape, ctypes.byref(ey), ctypes.byref(ex)), None)
+    return ey.value, ex.value
 
 
 def wave_ai_naive(ai_space: float, t_t: int) -> float:

@@ -68,16 +68,16 @@ def _try_schedule(op, T, shape, skew=0, zchunks=0):
         return False
 
 
-# --------------------------------------------------------------------------- C1
+# --------------------------------------------------------------------------- 64^3 so4 point source, 100 steps
 
 @pytest.fixture(scope="module")
-def c1_ref():
-    w = wi.c1()
+def ps64_ref():
+    w = wi.point_source_64()
     return w, _oracle(w)
 
 
-def test_c1_untiled_matches_oracle(c1_ref):
-    w, ref = c1_ref
+def test_point_source_64_untiled_matches_oracle(ps64_ref):
+    w, ref = ps64_ref
     op = _op(w, time_tile=-1)
     rec, fin = _run(op, w)
     assert np.abs(fin).max() > 1e-3, "solution is (nearly) zero"
@@ -88,8 +88,8 @@ def test_c1_untiled_matches_oracle(c1_ref):
 
 
 @pytest.mark.parametrize("T", [1, 2, 4])
-def test_c1_tiled_bitwise_equals_untiled(c1_ref, T):
-    w, ref = c1_ref
+def test_point_source_64_tiled_bitwise_equals_untiled(ps64_ref, T):
+    w, ref = ps64_ref
     op = _op(w, time_tile=-1)
     rec_u, fin_u = _run(op, w)
     for shape in (1, 2):

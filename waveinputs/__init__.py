@@ -147,48 +147,48 @@ def make_workload(name: str, shape, h: float, so: int, nt: int, nbl: int, c_phys
                     wavelet=wav, rec_xyz=rec, extra=dict(extra or {}))
 
 
-def c1(nt: int = 100, n: int = 64) -> Workload:
+def point_source_64(nt: int = 100, n: int = 64) -> Workload:
     """64^3, h=10 m, so4, constant 1500 m/s, no damping, 15 Hz Ricker at the
     grid centre, 64 receivers at depth index 2 across the middle row."""
     shape = (n, n, n)
-    w = make_workload("c1_64cube_so4", shape, 10.0, 4, nt, 0, constant_velocity(shape, 1500.0), 15.0,
+    w = make_workload("const_64cube_so4", shape, 10.0, 4, nt, 0, constant_velocity(shape, 1500.0), 15.0,
                       (n // 2, n // 2, n // 2), None)
     k = np.arange(n, dtype=np.float64)
     w.rec_xyz = np.stack([np.full_like(k, 2 * 10.0), np.full_like(k, (n // 2) * 10.0), k * 10.0], axis=1)
     return w
 
 
-def c2(nt: int = 1000, n: int = 512, seed: int = 2, so: int = 8, nbl: int = 40) -> Workload:
+def layered_512(nt: int = 1000, n: int = 512, seed: int = 2, so: int = 8, nbl: int = 40) -> Workload:
     """512^3 (+40-point layer), h=10 m, so8, 8 random horizontal layers in
     1.5-4.5 km/s, 10 Hz Ricker at depth 20 in the middle, a receiver line at
     depth 2 (dt fixed by c_max = 4.5 km/s at CFL 0.4)."""
     shape = (n, n, n)
     c = layered_velocity(shape, 8, seed)
-    return make_workload("c2_512cube_so8_layered", shape, 10.0, so, nt, nbl, c, 10.0,
+    return make_workload("layered_512cube_so8", shape, 10.0, so, nt, nbl, c, 10.0,
                          (min(20, n - 1), n // 2, n // 2), 2, c_max=C_MAX)
 
 
-def c3(so: int = 12, nt: int = 500, n: int = 768, seed: int = 3, nbl: int = 40) -> Workload:
+def smooth_768(so: int = 12, nt: int = 500, n: int = 768, seed: int = 3, nbl: int = 40) -> Workload:
     """768^3 (+40), h=12.5 m, smooth random velocity (sigma 8 cells), so12/16."""
     shape = (n, n, n)
     c = smooth_random_velocity(shape, seed)
-    return make_workload("c3_768cube_so%d_smooth" % so, shape, 12.5, so, nt, nbl, c, 10.0,
+    return make_workload("smooth_768cube_so%d" % so, shape, 12.5, so, nt, nbl, c, 10.0,
                          (min(20, n - 1), n // 2, n // 2), 2, c_max=C_MAX)
 
 
-def c4(nt: int = 2000, n: int = 256, seed: int = 4, nbl: int = 40, ckpt_every: int = 50) -> dict:
+def gradient_256(nt: int = 2000, n: int = 256, seed: int = 4, nbl: int = 40, ckpt_every: int = 50) -> dict:
     """Adjoint-gradient problem: smooth random true model, constant 2 km/s
     starting model, one Ricker shot at depth 20, 256 receivers at depth 2."""
     shape = (n, n, n)
     c_true = smooth_random_velocity(shape, seed)
-    true = make_workload("c4_256cube_so8_true", shape, 10.0, 8, nt, nbl, c_true, 10.0,
+    true = make_workload("smooth_256cube_so8_true", shape, 10.0, 8, nt, nbl, c_true, 10.0,
                          (min(20, n - 1), n // 2, n // 2), 2, c_max=C_MAX)
-    init = make_workload("c4_256cube_so8_init", shape, 10.0, 8, nt, nbl, constant_velocity(shape, 2000.0),
+    init = make_workload("const2000_256cube_so8_init", shape, 10.0, 8, nt, nbl, constant_velocity(shape, 2000.0),
                          10.0, (min(20, n - 1), n // 2, n // 2), 2, c_max=C_MAX)
     return {"true": true, "init": init, "ckpt_every": ckpt_every}
 
 
-def c5(nshots: int = 32, nt: int = 800, seed: int = 5, sizes=None) -> list:
+def shot_batch(nshots: int = 32, nt: int = 800, seed: int = 5, sizes=None) -> list:
     """Batch of independent shots: per-axis sizes from {128, 144, ..., 320},
     space order alternating 4/8, per-shot smooth random model, random source
     (interior, depth >= 2 radius), receiver line at depth 2, no layer."""
@@ -202,6 +202,6 @@ def c5(nshots: int = 32, nt: int = 800, seed: int = 5, sizes=None) -> list:
         src = (int(rng.integers(2 * r, shp[0] - 2 * r)), int(rng.integers(2 * r, shp[1] - 2 * r)),
                int(rng.integers(2 * r, shp[2] - 2 * r)))
         c = smooth_random_velocity(shp, seed * 1000 + i)
-        w = make_workload("c5_shot%02d" % i, shp, 10.0, so, nt, 0, c, 10.0, src, 2, c_max=C_MAX)
+        w = make_workload("batch_shot%02d" % i, shp, 10.0, so, nt, 0, c, 10.0, src, 2, c_max=C_MAX)
         out.append(w)
     return out
