@@ -216,6 +216,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512, help="physical grid edge of the forward workload")
     ap.add_argument("--nt", type=int, default=1000)
+    ap.add_argument("--so", type=int, default=8, help="space order of the forward workload")
     ap.add_argument("--T", type=int, default=0, help="time-tile depth (0: autotune, -1: untiled)")
     ap.add_argument("--shape", type=int, default=1)
     ap.add_argument("--zchunks", type=int, default=0)
@@ -223,7 +224,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="first run a plain 1 GiB device copy (reference for the traffic counters)")
+                    help="first run plain device copies of known size (reference for the traffic counters)")
     ap.add_argument("--quick", action="store_true", help="small sizes for a functional check")
     args = ap.parse_args()
 
@@ -243,22 +244,23 @@ def main():
     if args.quick:
         args.n, args.nt = 128, 100
 
-    if args.copy_calibration:
-        a = torch.empty(2 ** 28, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-        log("copy calibration: 3 copies of 1 GiB")
-
     # ---------------------------------------------------------------- forward, tuned schedule
     t0 = time.time()
-    w = wi.layered_512(nt=args.nt, n=args.n)
+    w = wi.layered_512(nt=args.nt, n=args.n, so=args.so)
     log("workload %s shape %s nt %d (%.1f s to generate)" % (w.name, w.shape, w.nt, time.time() - t0))
     m = torch.from_numpy(w.m).to(dev)
     wav = torch.from_numpy(w.wavelet).to(dev)
     op = WaveOp(w.shape, w.spacing, w.dt, w.so, m, nbl=w.nbl, sigma_max=w.sigma_max, time_tile=-1)
+    if args.copy_calibration:
+        # zero steps with an initial and a final state: four plain copies of
+        # N floats (one time level each) through the library's copy kernel,
+        # one float per lane like the sweep's own accesses
+        x = torch.zeros((2,) + tuple(w.shape), dtype=torch.float32, device=dev)
+        for _ in range(3):
+            op.forward(0, u_init=x, want_final=True)
+        torch.cuda.synchronize()
+        del x
+        log("copy calibration: 12 copies of %d bytes" % (w.npts * 4))
     if args.T != 0:
         op.set_schedule(args.T, 0, args.shape, args.zchunks)
     else:

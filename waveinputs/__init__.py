@@ -151,7 +151,7 @@ def point_source_64(nt: int = 100, n: int = 64) -> Workload:
     """64^3, h=10 m, so4, constant 1500 m/s, no damping, 15 Hz Ricker at the
     grid centre, 64 receivers at depth index 2 across the middle row."""
     shape = (n, n, n)
-    w = make_workload("const_64cube_so4", shape, 10.0, 4, nt, 0, constant_velocity(shape, 1500.0), 15.0,
+    w = make_workload("const_%dcube_so4" % n, shape, 10.0, 4, nt, 0, constant_velocity(shape, 1500.0), 15.0,
                       (n // 2, n // 2, n // 2), None)
     k = np.arange(n, dtype=np.float64)
     w.rec_xyz = np.stack([np.full_like(k, 2 * 10.0), np.full_like(k, (n // 2) * 10.0), k * 10.0], axis=1)
@@ -164,7 +164,7 @@ def layered_512(nt: int = 1000, n: int = 512, seed: int = 2, so: int = 8, nbl: i
     depth 2 (dt fixed by c_max = 4.5 km/s at CFL 0.4)."""
     shape = (n, n, n)
     c = layered_velocity(shape, 8, seed)
-    return make_workload("layered_512cube_so8", shape, 10.0, so, nt, nbl, c, 10.0,
+    return make_workload("layered_%dcube_so%d" % (n, so), shape, 10.0, so, nt, nbl, c, 10.0,
                          (min(20, n - 1), n // 2, n // 2), 2, c_max=C_MAX)
 
 
@@ -172,7 +172,7 @@ def smooth_768(so: int = 12, nt: int = 500, n: int = 768, seed: int = 3, nbl: in
     """768^3 (+40), h=12.5 m, smooth random velocity (sigma 8 cells), so12/16."""
     shape = (n, n, n)
     c = smooth_random_velocity(shape, seed)
-    return make_workload("smooth_768cube_so%d" % so, shape, 12.5, so, nt, nbl, c, 10.0,
+    return make_workload("smooth_%dcube_so%d" % (n, so), shape, 12.5, so, nt, nbl, c, 10.0,
                          (min(20, n - 1), n // 2, n // 2), 2, c_max=C_MAX)
 
 
@@ -181,9 +181,9 @@ def gradient_256(nt: int = 2000, n: int = 256, seed: int = 4, nbl: int = 40, ckp
     starting model, one Ricker shot at depth 20, 256 receivers at depth 2."""
     shape = (n, n, n)
     c_true = smooth_random_velocity(shape, seed)
-    true = make_workload("smooth_256cube_so8_true", shape, 10.0, 8, nt, nbl, c_true, 10.0,
+    true = make_workload("smooth_%dcube_so8_true" % n, shape, 10.0, 8, nt, nbl, c_true, 10.0,
                          (min(20, n - 1), n // 2, n // 2), 2, c_max=C_MAX)
-    init = make_workload("const2000_256cube_so8_init", shape, 10.0, 8, nt, nbl, constant_velocity(shape, 2000.0),
+    init = make_workload("const2000_%dcube_so8_init" % n, shape, 10.0, 8, nt, nbl, constant_velocity(shape, 2000.0),
                          10.0, (min(20, n - 1), n // 2, n // 2), 2, c_max=C_MAX)
     return {"true": true, "init": init, "ckpt_every": ckpt_every}
 
