@@ -10,9 +10,9 @@
  * OpenMP is used only over independent grid points (results do not depend on
  * the thread count).
  *
- * What is computed (the paper evaluates "acoustic wave equation operators"
- * (evaluation chapter, AWE section) but never prints their discretisation,
- * so the scheme below is the standard one for  m u_tt + damp u_t = lap u + q):
+ * What is computed (the paper's evaluation chapter, AWE section, measures an
+ * acoustic-wave operator but never prints its discretisation, so the scheme
+ * below is the standard one for  m u_tt + damp u_t = lap u + q):
  *
  *   coefficients  c_j = 2(-1)^{j+1} (k!)^2 / (j^2 (k-j)! (k+j)!),  j=1..k,
  *                 c_0 = -2 sum_j c_j,  k = space_order/2  (central second
