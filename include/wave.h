@@ -103,10 +103,11 @@ wave_status wave_set_schedule(wave_ctx* ctx, int32_t time_tile, int32_t skew, in
 wave_status wave_get_schedule(const wave_ctx* ctx, int32_t* time_tile, int32_t* skew, int32_t* tile_shape,
                               int32_t* zchunks);
 
-/* Scratch bytes needed by wave_forward (adjoint = 0) or by wave_forward with
- * checkpoints followed by wave_adjoint_grad (adjoint = 1) for nt steps with
- * nsrc sources and nrec receivers; ckpt_every = K > 0 keeps a checkpoint of
- * (u^{cK}, u^{cK-1}) for every segment. */
+/* Scratch bytes needed by wave_forward (adjoint = 0), by wave_forward with
+ * checkpoints followed by wave_adjoint_grad (adjoint = 1), or by one shot of
+ * wave_batch with a gradient (adjoint = 2: also the residual traces) for nt
+ * steps with nsrc sources and nrec receivers; ckpt_every = K > 0 keeps a
+ * checkpoint of (u^{cK}, u^{cK-1}) for every segment. */
 size_t wave_scratch_bytes(const wave_ctx* ctx, int32_t nt, int32_t nsrc, int32_t nrec, int32_t ckpt_every,
                           int32_t adjoint);
 
@@ -143,17 +144,36 @@ wave_status wave_adjoint_grad(wave_ctx* ctx, int32_t nt,
                               float* grad_m_dev, float* grad_wavelet_dev,
                               int32_t ckpt_every, int32_t reuse, void* scratch_dev, size_t scratch_bytes);
 
-/* Many independent shots (own grids, orders, models, schedules) advanced
- * together: every time window of every shot is one kernel launch per
- * (radius, depth, shape) group, the whole sequence captured once into a HIP
- * graph and replayed.  Forward only when grad_m is NULL; otherwise forward
- * with checkpoints, then adjoint and gradient for every shot.  Arrays are
- * per shot (length nshots); scratch[i] sized by wave_scratch_bytes.
- * Stream: that of ctxs[0] (all contexts must share it). */
+/* Many independent shots advanced together, for example the sources of one
+ * survey (the paper leaves multi-operator batching to future work; this is
+ * the GPU form of running many small operators at full occupancy).  Every
+ * shot is its own context (own grid, order, model, schedule); all contexts
+ * share the stream of ctxs[0].  Per-shot arrays have length nshots:
+ *   nsrc, src_xyz, wavelet_dev, nrec, rec_xyz   as in wave_forward
+ *   rec_dev      device [nt][nrec] out: modelled traces
+ *   grad_m_dev   NULL: forward only.  Otherwise device [N] out per shot: the
+ *                gradient of J = 1/2 sum |rec - dobs|^2 with respect to m
+ *                (forward with checkpoints every ckpt_every >= 1 steps, the
+ *                residual, recompute, adjoint and imaging, as wave_adjoint_grad)
+ *   dobs_dev     device [nt][nrec] observed traces (with grad_m_dev only)
+ *   scratch_dev  device, scratch_bytes[i] >= wave_scratch_bytes(ctx_i, nt,
+ *                nsrc_i, nrec_i, ckpt_every if gradient else 0, 2 if gradient else 0)
+ * Each shot's operations are recorded and the pending sweeps of all shots
+ * are merged: one launch per group of shots with equal (radius, depth,
+ * dim, tile shape, mode), at most 12 shots per launch, each workgroup
+ * finding its shot from the launch arguments.  The merged sequence is
+ * captured into a HIP graph and launched; a later call with the same
+ * arguments on contexts that no other call has touched since replays that
+ * graph without recording again (device inputs may change in between).
+ * Results are bitwise those of the per-shot calls.  Every shot's schedule
+ * must be the untiled sweep or T <= 2 (WAVE_EUNSUPPORTED otherwise); a
+ * context may appear once; calls on the same contexts must not overlap.
+ * Errors: WAVE_EINVAL (null arrays, duplicate context, different streams),
+ * WAVE_ENOMEM (scratch too small), WAVE_EHIP; the message is on ctxs[0]. */
 wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
                        const int32_t* nsrc, const double* const* src_xyz, const float* const* wavelet_dev,
                        const int32_t* nrec, const double* const* rec_xyz, float* const* rec_dev,
-                       const float* const* resid_dev, float* const* grad_m_dev,
+                       const float* const* dobs_dev, float* const* grad_m_dev,
                        int32_t ckpt_every, void* const* scratch_dev, const size_t* scratch_bytes);
 
 /* Autotune the schedule (T, skew, tile shape, zchunks) on this context's

@@ -31,12 +31,23 @@ FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH, "-ffp-contract=
 
 def sources():
     srcs = [os.path.join(CSRC, "wave_api.cpp")]
-    srcs += [os.path.join(CSRC, "wave_r%d_m%d.hip" % (r, m)) for r in range(1, 9) for m in range(3)]
+    srcs += [os.path.join(CSRC, "wave_r%d_%s%d.hip" % (r, k, m)) for r in range(1, 9) for k in "mb" for m in range(3)]
     return srcs
 
 
-def _compile(src: str) -> str:
+def _headers():
+    hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".inc"))]
+    inc = os.path.join(ROOT, "include")
+    hs += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+    return hs
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj):
+        newest = max(os.path.getmtime(f) for f in _headers() + [src, __file__])
+        if os.path.getmtime(obj) > newest:
+            return obj
     cmd = [HIPCC, "-c", "-x", "hip", src, "-o", obj] + FLAGS
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -44,7 +55,9 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 0, verbose: bool = True) -> str:
+def build(jobs: int = 0, verbose: bool = True, incremental: bool = False) -> str:
+    """Compile every translation unit (incremental=True: only those older
+    than their sources or any header) and link libwavett.so."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
     srcs = sources()
@@ -52,7 +65,7 @@ def build(jobs: int = 0, verbose: bool = True) -> str:
     cost = {"wave_r4": 0, "wave_r3": 1, "wave_r2": 2}
     srcs.sort(key=lambda s: cost.get(os.path.basename(s)[:7], 3))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -65,4 +78,4 @@ def build(jobs: int = 0, verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)

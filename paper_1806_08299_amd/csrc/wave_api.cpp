@@ -5,10 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -20,6 +22,26 @@
 using namespace wavett;
 
 // =========================================================== context
+
+// One device operation of a driver, recorded instead of launched while the
+// context belongs to a batch: a sweep launch (merged with the other shots'
+// sweeps of the same instantiation) or any other kernel.
+struct RecOp {
+  bool sweep = false;
+  int R = 0, kind = 0, T = 0, dim = 3, mode = 0, shape = 0;
+  size_t lds = 0;
+  SweepArgs A{};
+  std::function<hipError_t(hipStream_t)> fn;
+};
+struct Recorder {
+  std::vector<RecOp> ops;
+};
+// Captured batch, replayed while the call and every context are unchanged.
+struct BatchGraph {
+  std::vector<uint64_t> sig;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 struct wave_ctx {
   wave_desc d;
@@ -42,7 +64,13 @@ struct wave_ctx {
     const void* scratch = nullptr;
     std::vector<double> src, rec;
   } ck;
-  SweepAux aux_host[4];   // sources of the per-call table copies
+  SweepAux aux_host[4];          // sources of the per-call table copies
+  std::vector<char> stage[4];    // host images of the point tables (live sources of their copies)
+  Recorder* rec = nullptr;       // non-null: device operations are recorded, not launched
+  uint64_t id = 0;               // unique per context of the process
+  uint64_t gen = 0;              // bumped by every call that rewrites the caller's scratch
+  BatchGraph* graph = nullptr;   // last batch led by this context
+  hipStream_t cap = nullptr;     // stream the batch is captured on (the caller's may be the null stream)
   std::string err;
 };
 
@@ -62,6 +90,20 @@ wave_status fail(wave_ctx* c, wave_status s, const std::string& msg) {
     if (_e != hipSuccess)                                                           \
       return fail(ctx, WAVE_EHIP, std::string(#expr) + ": " + hipGetErrorString(_e)); \
   } while (0)
+
+// Launch a non-sweep kernel now, or record it when the context is recording.
+template <class F>
+wave_status enq(wave_ctx* c, F f) {
+  if (c->rec) {
+    RecOp op;
+    op.fn = f;
+    c->rec->ops.push_back(std::move(op));
+    return WAVE_OK;
+  }
+  const hipError_t e = f(c->stream);
+  if (e != hipSuccess) return fail(c, WAVE_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return WAVE_OK;
+}
 
 // Central second-derivative weights of order so, unit spacing (closed form).
 void fd_weights(int so, double* c) {
@@ -301,16 +343,18 @@ dim3 grid1d(int64_t n) {
 
 wave_status fill(wave_ctx* c, float* p, int64_t n, float v) {
   if (n <= 0) return WAVE_OK;
-  hipLaunchKernelGGL(k_fill, grid1d(n), dim3(256), 0, c->stream, p, n, v);
-  HIP_TRY(c, hipGetLastError());
-  return WAVE_OK;
+  return enq(c, [=](hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, grid1d(n), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+  });
 }
 
 wave_status copy(wave_ctx* c, const float* s, float* d, int64_t n) {
   if (n <= 0) return WAVE_OK;
-  hipLaunchKernelGGL(k_copy, grid1d(n), dim3(256), 0, c->stream, s, d, n);
-  HIP_TRY(c, hipGetLastError());
-  return WAVE_OK;
+  return enq(c, [=](hipStream_t st) {
+    hipLaunchKernelGGL(k_copy, grid1d(n), dim3(256), 0, st, s, d, n);
+    return hipGetLastError();
+  });
 }
 
 // ----------------------------------------------------------- schedule
@@ -398,6 +442,20 @@ wave_status launch_window(wave_ctx* c, const Plan& p, SweepArgs A) {
   int mode = MODE_FWD;
   if (A.grad) mode = MODE_ADJ;
   else if (A.hist) mode = MODE_HIST;
+  if (c->rec) {
+    RecOp op;
+    op.sweep = true;
+    op.R = c->R;
+    op.kind = p.kind;
+    op.T = p.T;
+    op.dim = c->dim;
+    op.mode = mode;
+    op.shape = p.shape;
+    op.lds = p.lds;
+    op.A = A;
+    c->rec->ops.push_back(std::move(op));
+    return WAVE_OK;
+  }
   hipError_t e = launch_sweep(c->R, p.kind, p.T, c->dim, mode, p.shape, A, grid, p.lds, c->stream);
   if (e != hipSuccess) return fail(c, WAVE_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
   return WAVE_OK;
@@ -485,6 +543,7 @@ struct Layout {
   size_t adj_inj = 0, adj_smp = 0;   // adjoint forcing [nt][npts_rec], samples [nt][npts_src]
   size_t hist = 0;                   // [K][N]
   size_t adj_w = 0;                  // [4][N]
+  size_t resid = 0;                  // batched gradient: residual [nt][nrec]
   size_t total = 0;
   int nseg = 0;
 };
@@ -509,6 +568,9 @@ Layout layout(const wave_ctx* c, int nt, int nsrc, int nrec, int K, int adjoint)
     L.hist = o; o += align_up(sizeof(float) * (size_t)Kh * c->N);
     L.adj_w = o; o += align_up(sizeof(float) * 4 * (size_t)c->N);
   }
+  if (adjoint == 2) {
+    L.resid = o; o += align_up(sizeof(float) * (size_t)nt * (size_t)nrec);
+  }
   L.total = o;
   return L;
 }
@@ -529,19 +591,22 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
   build_points(c, nsrc, src, PS);
   build_points(c, rec_out ? nrec : 0, rec, PR);
   DevPoints DS, DR;
-  std::vector<char> h1, h2;
   char* cur = scratch + L.tab_src;
-  wave_status s = upload_points(c, PS, cur, DS, h1);
+  wave_status s = upload_points(c, PS, cur, DS, c->stage[0]);
   if (s) return s;
   cur = scratch + L.tab_rec;
-  s = upload_points(c, PR, cur, DR, h2);
+  s = upload_points(c, PR, cur, DR, c->stage[1]);
   if (s) return s;
   float* table = (float*)(scratch + L.inj);
   float* samp = (float*)(scratch + L.smp);
   if (PS.npts > 0) {
-    hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * PS.npts), dim3(256), 0, c->stream, wav, nsrc, nt,
-                       DS.pt_ptr, DS.pt_src, DS.pt_w, PS.npts, 1.0f, table);
-    HIP_TRY(c, hipGetLastError());
+    const int np = PS.npts;
+    s = enq(c, [=](hipStream_t st) {
+      hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * np), dim3(256), 0, st, wav, nsrc, nt, DS.pt_ptr,
+                         DS.pt_src, DS.pt_w, np, 1.0f, table);
+      return hipGetLastError();
+    });
+    if (s) return s;
   }
   if (PR.npts > 0) {
     s = fill(c, samp, (int64_t)nt * PR.npts, 0.0f);
@@ -573,9 +638,13 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
   }
   if (rec_out && nrec > 0) {
     if (PR.npts > 0) {
-      hipLaunchKernelGGL(k_reduce_samples, grid1d((int64_t)nt * nrec), dim3(256), 0, c->stream, samp, PR.npts, nt,
-                         DR.pos_ptr, DR.corner_pt, DR.corner_w, nrec, 1.0f, rec_out);
-      HIP_TRY(c, hipGetLastError());
+      const int np = PR.npts;
+      s = enq(c, [=](hipStream_t st) {
+        hipLaunchKernelGGL(k_reduce_samples, grid1d((int64_t)nt * nrec), dim3(256), 0, st, samp, np, nt, DR.pos_ptr,
+                           DR.corner_pt, DR.corner_w, nrec, 1.0f, rec_out);
+        return hipGetLastError();
+      });
+      if (s) return s;
     } else {
       if ((s = fill(c, rec_out, (int64_t)nt * nrec, 0.0f))) return s;
     }
@@ -614,6 +683,21 @@ hipError_t launch_sweep(int R, int kind, int T, int dim, int mode, int shape, co
     return mode == 0 ? launch_sweep_r##RR##_m0(kind, T, dim, shape, A, grid, lds, s)  \
          : mode == 1 ? launch_sweep_r##RR##_m1(kind, T, dim, shape, A, grid, lds, s)  \
                      : launch_sweep_r##RR##_m2(kind, T, dim, shape, A, grid, lds, s);
+  switch (R) {
+    WAVE_CASE(1) WAVE_CASE(2) WAVE_CASE(3) WAVE_CASE(4) WAVE_CASE(5) WAVE_CASE(6) WAVE_CASE(7) WAVE_CASE(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef WAVE_CASE
+}
+
+hipError_t launch_batch(int R, int kind, int T, int dim, int mode, int shape, const BatchArgs& B, dim3 grid,
+                        size_t lds, hipStream_t s) {
+  if (mode < 0 || mode > 2) return hipErrorInvalidValue;
+#define WAVE_CASE(RR)                                                                  \
+  case RR:                                                                             \
+    return mode == 0 ? launch_batch_r##RR##_m0(kind, T, dim, shape, B, grid, lds, s)  \
+         : mode == 1 ? launch_batch_r##RR##_m1(kind, T, dim, shape, B, grid, lds, s)  \
+                     : launch_batch_r##RR##_m2(kind, T, dim, shape, B, grid, lds, s);
   switch (R) {
     WAVE_CASE(1) WAVE_CASE(2) WAVE_CASE(3) WAVE_CASE(4) WAVE_CASE(5) WAVE_CASE(6) WAVE_CASE(7) WAVE_CASE(8)
     default: return hipErrorInvalidValue;
@@ -736,7 +820,9 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
   if (s != WAVE_OK) return s;
   if (!m || !state) return WAVE_EINVAL;
   if (state_bytes < wave_state_bytes(d)) return WAVE_ENOMEM;
+  static std::atomic<uint64_t> next_id{0};
   wave_ctx* c = new wave_ctx();
+  c->id = ++next_id;
   c->d = *d;
   c->R = d->space_order / 2;
   c->dim = d->ndim;
@@ -802,7 +888,16 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
   return WAVE_OK;
 }
 
-void wave_destroy(wave_ctx* c) { delete c; }
+void wave_destroy(wave_ctx* c) {
+  if (!c) return;
+  if (c->graph) {
+    if (c->graph->exec) (void)hipGraphExecDestroy(c->graph->exec);
+    if (c->graph->graph) (void)hipGraphDestroy(c->graph->graph);
+    delete c->graph;
+  }
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+}
 
 size_t wave_scratch_bytes(const wave_ctx* c, int32_t nt, int32_t nsrc, int32_t nrec, int32_t K, int32_t adjoint) {
   if (!c || nt < 0 || nsrc < 0 || nrec < 0 || K < 0) return 0;
@@ -821,6 +916,7 @@ wave_status wave_forward(wave_ctx* c, int32_t nt, int32_t nsrc, const double* sr
   if (nt > 0 && nsrc > 0 && !wav) return fail(c, WAVE_EINVAL, "null wavelet");
   const Layout L = layout(c, nt, nsrc, nrec, K, 0);
   if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  c->gen++;
   s = forward_core(c, nt, nsrc, src, wav, nrec, rec, rec_out, u_init, u_final, K, (char*)scratch, L);
   if (s != WAVE_OK) return s;
   if (K > 0 && !u_init) {
@@ -835,51 +931,43 @@ wave_status wave_forward(wave_ctx* c, int32_t nt, int32_t nsrc, const double* sr
   return WAVE_OK;
 }
 
-wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const double* src, const float* wav,
-                              int32_t nrec, const double* rec, const float* resid, float* grad_m, float* grad_q,
-                              int32_t K, int32_t reuse, void* scratch, size_t scratch_bytes) {
-  if (!c) return WAVE_EINVAL;
-  c->err.clear();
-  if (nt < 0 || K < 1) return fail(c, WAVE_EINVAL, "need nt >= 0 and a checkpoint interval >= 1");
-  if (!grad_m) return fail(c, WAVE_EINVAL, "null grad_m");
-  if (nt > 0 && nrec > 0 && !resid) return fail(c, WAVE_EINVAL, "null residual");
+// Recompute + adjoint + imaging over every checkpoint segment, given the
+// checkpoints of a forward with interval K in the scratch of layout L.  Point
+// tables are rebuilt into the same scratch regions: for the same coordinates
+// their bytes equal those of the forward (so a recorded forward still reads
+// what it wrote).
+static wave_status adjoint_core(wave_ctx* c, int nt, int nsrc, const double* src, const float* wav, int nrec,
+                                const double* rec, const float* resid, float* grad_m, float* grad_q, int K, char* sc,
+                                const Layout& L) {
   wave_status s;
-  if ((s = validate_coords(c, nsrc, src)) || (s = validate_coords(c, nrec, rec))) return s;
-  if (nt > 0 && nsrc > 0 && !wav) return fail(c, WAVE_EINVAL, "null wavelet");
-  const Layout L = layout(c, nt, nsrc, nrec, K, 1);
-  if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
-  char* sc = (char*)scratch;
-  if (reuse) {
-    const bool ok = c->ck.valid && c->ck.nt == nt && c->ck.K == K && c->ck.nsrc == nsrc && c->ck.scratch == scratch &&
-                    std::equal(c->ck.src.begin(), c->ck.src.end(), src);
-    if (!ok) return fail(c, WAVE_ESTATE, "no matching checkpoints from a preceding forward");
-  } else {
-    s = forward_core(c, nt, nsrc, src, wav, 0, nullptr, nullptr, nullptr, nullptr, K, sc, L);
-    if (s != WAVE_OK) return s;
-  }
-  c->ck.valid = false;
-  // source table (for injection during recompute and for grad_q sampling)
   PointTable PS, PR;
   build_points(c, nsrc, src, PS);
   build_points(c, nrec, rec, PR);
   DevPoints DS, DR;
-  std::vector<char> h1, h2;
   char* cur = sc + L.tab_src;
-  if ((s = upload_points(c, PS, cur, DS, h1))) return s;
+  if ((s = upload_points(c, PS, cur, DS, c->stage[2]))) return s;
   cur = sc + L.tab_rec;
-  if ((s = upload_points(c, PR, cur, DR, h2))) return s;
+  if ((s = upload_points(c, PR, cur, DR, c->stage[3]))) return s;
   float* table = (float*)(sc + L.inj);
   if (PS.npts > 0) {
-    hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * PS.npts), dim3(256), 0, c->stream, wav, nsrc, nt,
-                       DS.pt_ptr, DS.pt_src, DS.pt_w, PS.npts, 1.0f, table);
-    HIP_TRY(c, hipGetLastError());
+    const int np = PS.npts;
+    s = enq(c, [=](hipStream_t st) {
+      hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * np), dim3(256), 0, st, wav, nsrc, nt, DS.pt_ptr,
+                         DS.pt_src, DS.pt_w, np, 1.0f, table);
+      return hipGetLastError();
+    });
+    if (s) return s;
   }
   float* atab = (float*)(sc + L.adj_inj);
   if (PR.npts > 0) {
     const float inv_dt2 = (float)(1.0 / (c->d.dt * c->d.dt));
-    hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * PR.npts), dim3(256), 0, c->stream, resid, nrec, nt,
-                       DR.pt_ptr, DR.pt_src, DR.pt_w, PR.npts, inv_dt2, atab);
-    HIP_TRY(c, hipGetLastError());
+    const int np = PR.npts;
+    s = enq(c, [=](hipStream_t st) {
+      hipLaunchKernelGGL(k_forcing_table, grid1d((int64_t)nt * np), dim3(256), 0, st, resid, nrec, nt, DR.pt_ptr,
+                         DR.pt_src, DR.pt_w, np, inv_dt2, atab);
+      return hipGetLastError();
+    });
+    if (s) return s;
   }
   float* asmp = (float*)(sc + L.adj_smp);
   if (grad_q && PS.npts > 0) {
@@ -916,9 +1004,14 @@ wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const doubl
   }
   if (grad_q && nsrc > 0) {
     if (PS.npts > 0) {
-      hipLaunchKernelGGL(k_reduce_samples, grid1d((int64_t)nt * nsrc), dim3(256), 0, c->stream, asmp, PS.npts, nt,
-                         DS.pos_ptr, DS.corner_pt, DS.corner_w, nsrc, (float)(c->d.dt * c->d.dt), grad_q);
-      HIP_TRY(c, hipGetLastError());
+      const int np = PS.npts;
+      const float dt2 = (float)(c->d.dt * c->d.dt);
+      s = enq(c, [=](hipStream_t st) {
+        hipLaunchKernelGGL(k_reduce_samples, grid1d((int64_t)nt * nsrc), dim3(256), 0, st, asmp, np, nt, DS.pos_ptr,
+                           DS.corner_pt, DS.corner_w, nsrc, dt2, grad_q);
+        return hipGetLastError();
+      });
+      if (s) return s;
     } else if ((s = fill(c, grad_q, (int64_t)nt * nsrc, 0.0f))) {
       return s;
     }
@@ -926,14 +1019,215 @@ wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const doubl
   return WAVE_OK;
 }
 
+wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const double* src, const float* wav,
+                              int32_t nrec, const double* rec, const float* resid, float* grad_m, float* grad_q,
+                              int32_t K, int32_t reuse, void* scratch, size_t scratch_bytes) {
+  if (!c) return WAVE_EINVAL;
+  c->err.clear();
+  if (nt < 0 || K < 1) return fail(c, WAVE_EINVAL, "need nt >= 0 and a checkpoint interval >= 1");
+  if (!grad_m) return fail(c, WAVE_EINVAL, "null grad_m");
+  if (nt > 0 && nrec > 0 && !resid) return fail(c, WAVE_EINVAL, "null residual");
+  wave_status s;
+  if ((s = validate_coords(c, nsrc, src)) || (s = validate_coords(c, nrec, rec))) return s;
+  if (nt > 0 && nsrc > 0 && !wav) return fail(c, WAVE_EINVAL, "null wavelet");
+  const Layout L = layout(c, nt, nsrc, nrec, K, 1);
+  if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  char* sc = (char*)scratch;
+  if (reuse) {
+    const bool ok = c->ck.valid && c->ck.nt == nt && c->ck.K == K && c->ck.nsrc == nsrc && c->ck.scratch == scratch &&
+                    std::equal(c->ck.src.begin(), c->ck.src.end(), src);
+    if (!ok) return fail(c, WAVE_ESTATE, "no matching checkpoints from a preceding forward");
+  }
+  c->gen++;
+  if (!reuse) {
+    s = forward_core(c, nt, nsrc, src, wav, 0, nullptr, nullptr, nullptr, nullptr, K, sc, L);
+    if (s != WAVE_OK) return s;
+  }
+  c->ck.valid = false;
+  return adjoint_core(c, nt, nsrc, src, wav, nrec, rec, resid, grad_m, grad_q, K, sc, L);
+}
+
+// Replays the recorded operations of every shot on `st` in one interleaved
+// sequence: each shot's non-sweep operations run in its own order; the
+// pending sweeps of all shots are merged, one launch per group of equal
+// (radius, kind, depth, dim, mode, shape), at most kMaxBatch shots each.  A
+// group of one uses the single-context kernel.
+static wave_status replay_merged(wave_ctx* lead, std::vector<Recorder>& recs, hipStream_t st) {
+  const size_t n = recs.size();
+  std::vector<size_t> pos(n, 0);
+  auto same = [](const RecOp& x, const RecOp& y) {
+    return x.R == y.R && x.kind == y.kind && x.T == y.T && x.dim == y.dim && x.mode == y.mode && x.shape == y.shape;
+  };
+  for (;;) {
+    for (size_t i = 0; i < n; ++i) {
+      auto& ops = recs[i].ops;
+      while (pos[i] < ops.size() && !ops[pos[i]].sweep) {
+        const hipError_t e = ops[pos[i]].fn(st);
+        if (e != hipSuccess) return fail(lead, WAVE_EHIP, std::string("batched kernel: ") + hipGetErrorString(e));
+        ++pos[i];
+      }
+    }
+    std::vector<size_t> pend;
+    for (size_t i = 0; i < n; ++i)
+      if (pos[i] < recs[i].ops.size()) pend.push_back(i);
+    if (pend.empty()) return WAVE_OK;
+    std::vector<bool> done(pend.size(), false);
+    for (size_t g = 0; g < pend.size(); ++g) {
+      if (done[g]) continue;
+      const RecOp& key = recs[pend[g]].ops[pos[pend[g]]];
+      std::vector<size_t> grp;
+      for (size_t h = g; h < pend.size() && grp.size() < (size_t)kMaxBatch; ++h)
+        if (!done[h] && same(recs[pend[h]].ops[pos[pend[h]]], key)) {
+          grp.push_back(pend[h]);
+          done[h] = true;
+        }
+      hipError_t e;
+      if (grp.size() == 1) {
+        const RecOp& op = recs[grp[0]].ops[pos[grp[0]]];
+        e = launch_sweep(op.R, op.kind, op.T, op.dim, op.mode, op.shape, op.A, dim3((unsigned)op.A.nblocks), op.lds, st);
+      } else {
+        BatchArgs B{};
+        B.n = (int32_t)grp.size();
+        int64_t total = 0;
+        for (size_t k = 0; k < grp.size(); ++k) {
+          const RecOp& op = recs[grp[k]].ops[pos[grp[k]]];
+          B.off[k] = (int32_t)total;
+          B.a[k] = op.A;
+          total += op.A.nblocks;
+        }
+        if (total >= (int64_t(1) << 31)) return fail(lead, WAVE_EUNSUPPORTED, "batched grid too large");
+        B.off[grp.size()] = (int32_t)total;
+        e = launch_batch(key.R, key.kind, key.T, key.dim, key.mode, key.shape, B, dim3((unsigned)total), key.lds, st);
+      }
+      if (e != hipSuccess) return fail(lead, WAVE_EHIP, std::string("batched sweep: ") + hipGetErrorString(e));
+      for (size_t k : grp) ++pos[k];
+    }
+  }
+}
+
 wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const int32_t* nsrc,
                        const double* const* src_xyz, const float* const* wavelet_dev, const int32_t* nrec,
-                       const double* const* rec_xyz, float* const* rec_dev, const float* const* resid_dev,
-                       float* const* grad_m_dev, int32_t ckpt_every, void* const* scratch_dev,
-                       const size_t* scratch_bytes) {
-  (void)ctxs; (void)nshots; (void)nt; (void)nsrc; (void)src_xyz; (void)wavelet_dev; (void)nrec; (void)rec_xyz;
-  (void)rec_dev; (void)resid_dev; (void)grad_m_dev; (void)ckpt_every; (void)scratch_dev; (void)scratch_bytes;
-  return WAVE_EUNSUPPORTED;
+                       const double* const* rec_xyz, float* const* rec_dev, const float* const* dobs_dev,
+                       float* const* grad_m_dev, int32_t K, void* const* scratch_dev, const size_t* scratch_bytes) {
+  if (!ctxs || nshots < 1 || !ctxs[0]) return WAVE_EINVAL;
+  wave_ctx* lead = ctxs[0];
+  lead->err.clear();
+  if (nt < 0) return fail(lead, WAVE_EINVAL, "negative nt");
+  if (!nsrc || !src_xyz || !wavelet_dev || !nrec || !rec_xyz || !rec_dev || !scratch_dev || !scratch_bytes)
+    return fail(lead, WAVE_EINVAL, "null per-shot array");
+  const bool grad = grad_m_dev != nullptr;
+  if (grad && (!dobs_dev || K < 1)) return fail(lead, WAVE_EINVAL, "gradient needs observed data and K >= 1");
+  const int Kf = grad ? K : 0;
+  const hipStream_t st = lead->stream;
+  std::vector<Layout> lay(nshots);
+  for (int i = 0; i < nshots; ++i) {
+    wave_ctx* c = ctxs[i];
+    if (!c) return fail(lead, WAVE_EINVAL, "null context");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(lead, WAVE_EINVAL, "a context appears twice in the batch");
+    if (c->stream != st) return fail(lead, WAVE_EINVAL, "all contexts of a batch must share one stream");
+    if (c->T > kBatchTmax) return fail(lead, WAVE_EUNSUPPORTED, "batched shots need the untiled sweep or depth <= 2");
+    wave_status s;
+    if ((s = validate_coords(c, nsrc[i], src_xyz[i])) || (s = validate_coords(c, nrec[i], rec_xyz[i])))
+      return fail(lead, s, "shot " + std::to_string(i) + ": " + c->err);
+    if (nt > 0 && nsrc[i] > 0 && !wavelet_dev[i]) return fail(lead, WAVE_EINVAL, "null wavelet");
+    if (nt > 0 && nrec[i] > 0 && !rec_dev[i]) return fail(lead, WAVE_EINVAL, "null receiver output");
+    if (grad && (!grad_m_dev[i] || (nt > 0 && nrec[i] > 0 && !dobs_dev[i])))
+      return fail(lead, WAVE_EINVAL, "null gradient or observed data");
+    lay[i] = layout(c, nt, nsrc[i], nrec[i], Kf, grad ? 2 : 0);
+    if (!scratch_dev[i] || scratch_bytes[i] < lay[i].total)
+      return fail(lead, WAVE_ENOMEM, "scratch buffer of shot " + std::to_string(i) + " too small");
+  }
+  // Everything the captured sequence depends on, including each context's
+  // generation (bumped by every call that rewrites its scratch).
+  auto signature = [&]() {
+    std::vector<uint64_t> sig = {(uint64_t)nshots, (uint64_t)nt, (uint64_t)Kf, (uint64_t)grad};
+    for (int i = 0; i < nshots; ++i) {
+      const wave_ctx* c = ctxs[i];
+      const uint64_t v[] = {c->id, c->gen, (uint64_t)c->T, (uint64_t)c->skew, (uint64_t)c->shape,
+                          (uint64_t)c->zchunks, (uint64_t)nsrc[i], (uint64_t)nrec[i],
+                          (uint64_t)(uintptr_t)wavelet_dev[i], (uint64_t)(uintptr_t)rec_dev[i],
+                          (uint64_t)(uintptr_t)(grad ? dobs_dev[i] : nullptr),
+                          (uint64_t)(uintptr_t)(grad ? grad_m_dev[i] : nullptr),
+                          (uint64_t)(uintptr_t)scratch_dev[i], (uint64_t)scratch_bytes[i]};
+      sig.insert(sig.end(), std::begin(v), std::end(v));
+      for (int k = 0; k < nsrc[i] * c->dim; ++k) {
+        uint64_t b;
+        std::memcpy(&b, &src_xyz[i][k], 8);
+        sig.push_back(b);
+      }
+      for (int k = 0; k < nrec[i] * c->dim; ++k) {
+        uint64_t b;
+        std::memcpy(&b, &rec_xyz[i][k], 8);
+        sig.push_back(b);
+      }
+    }
+    return sig;
+  };
+  // Same call on unchanged contexts: replay the captured graph.
+  if (lead->graph && lead->graph->exec && lead->graph->sig == signature()) {
+    HIP_TRY(lead, hipGraphLaunch(lead->graph->exec, st));
+    return WAVE_OK;
+  }
+  // Record every shot's operations (table uploads happen now, on the stream).
+  std::vector<Recorder> recs(nshots);
+  wave_status s = WAVE_OK;
+  for (int i = 0; i < nshots && s == WAVE_OK; ++i) {
+    wave_ctx* c = ctxs[i];
+    char* sc = (char*)scratch_dev[i];
+    c->err.clear();
+    c->ck.valid = false;
+    c->gen++;
+    c->rec = &recs[i];
+    s = forward_core(c, nt, nsrc[i], src_xyz[i], wavelet_dev[i], nrec[i], rec_xyz[i], rec_dev[i], nullptr, nullptr,
+                     Kf, sc, lay[i]);
+    if (s == WAVE_OK && grad) {
+      float* resid = (float*)(sc + lay[i].resid);
+      const float* rec = rec_dev[i];
+      const float* obs = dobs_dev[i];
+      const int64_t nn = (int64_t)nt * nrec[i];
+      if (nn > 0)
+        s = enq(c, [=](hipStream_t q) {
+          hipLaunchKernelGGL(k_sub, grid1d(nn), dim3(256), 0, q, rec, obs, resid, nn);
+          return hipGetLastError();
+        });
+      if (s == WAVE_OK)
+        s = adjoint_core(c, nt, nsrc[i], src_xyz[i], wavelet_dev[i], nrec[i], rec_xyz[i], resid, grad_m_dev[i],
+                         nullptr, Kf, sc, lay[i]);
+    }
+    c->rec = nullptr;
+    if (s != WAVE_OK && c != lead) s = fail(lead, s, "shot " + std::to_string(i) + ": " + c->err);
+  }
+  if (s != WAVE_OK) return s;
+  // Capture the merged sequence once and launch it.
+  if (lead->graph) {
+    if (lead->graph->exec) (void)hipGraphExecDestroy(lead->graph->exec);
+    if (lead->graph->graph) (void)hipGraphDestroy(lead->graph->graph);
+    delete lead->graph;
+    lead->graph = nullptr;
+  }
+  // Capture on a stream of our own (default priority): nothing runs while
+  // capturing; the graph is then launched on the caller's stream, after the
+  // table uploads made there during recording.
+  if (!lead->cap) HIP_TRY(lead, hipStreamCreateWithFlags(&lead->cap, hipStreamNonBlocking));
+  HIP_TRY(lead, hipStreamBeginCapture(lead->cap, hipStreamCaptureModeRelaxed));
+  s = replay_merged(lead, recs, lead->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(lead->cap, &g);
+  if (s != WAVE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (ec != hipSuccess) return fail(lead, WAVE_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(lead, WAVE_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+  }
+  lead->graph = new BatchGraph{signature(), g, x};
+  HIP_TRY(lead, hipGraphLaunch(x, st));
+  return WAVE_OK;
 }
 
 wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, void* scratch,
@@ -941,6 +1235,7 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
   if (!c || trial_steps < 1 || repeats < 1) return WAVE_EINVAL;
   const Layout L = layout(c, trial_steps, 0, 0, 0, 0);
   if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  c->gen++;
   struct Cand { int T, skew, shape, zc; };
   std::vector<Cand> cands;
   cands.push_back({-1, c->R, c->shape ? c->shape : 1, 0});

@@ -149,13 +149,45 @@ __device__ __forceinline__ float damp_term(int i, int n, int nbl, float coef) {
   return coef * (float)(d * d);
 }
 
-// Work item of this workgroup: tiles vary fastest, then axis-0 segments, so
+// Arguments of one launch: the windows of up to kMaxBatch independent shots
+// (same radius, depth, tile shape and mode) whose workgroups share one grid.
+// Shot s owns workgroups [off[s], off[s+1]).  Everything travels in the
+// kernel-argument segment (under 4 KiB), so a launch needs no device table
+// and every field is read with scalar loads from invariant memory.
+constexpr int kMaxBatch = 12;
+struct BatchArgs {
+  int32_t n;                       // shots in this launch, 1..kMaxBatch
+  int32_t off[kMaxBatch + 1];      // off[0] = 0, off[n] = grid size
+  SweepArgs a[kMaxBatch];
+};
+
+// Kernel argument of a single-context launch (SweepArgs, fields at static
+// offsets of the argument segment) or of a batched one (BatchArgs).
+template <bool BATCH> struct LaunchArgs { using type = SweepArgs; };
+template <> struct LaunchArgs<true> { using type = BatchArgs; };
+
+// The arguments of this workgroup's shot and its workgroup index within the
+// shot.  Batched: the shot is found by a fixed-trip scan over the prefix,
+// fully unrolled so that its scalar loads are issued together (wave-uniform).
+__device__ __forceinline__ const SweepArgs& shot_args(const SweepArgs& A, int& blk) {
+  blk = (int)blockIdx.x;
+  return A;
+}
+__device__ __forceinline__ const SweepArgs& shot_args(const BatchArgs& B, int& blk) {
+  int s = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxBatch; ++i) s += (i < B.n && (int)blockIdx.x >= B.off[i]) ? 1 : 0;
+  blk = (int)blockIdx.x - B.off[s];
+  return B.a[s];
+}
+
+// Work item `blk` of a shot: tiles vary fastest, then axis-0 segments, so
 // the workgroups resident at any moment cover one compact front of the grid
 // (neighbouring tiles re-read each other's halo columns from the shared
 // last-level cache while they are still there).
-__device__ __forceinline__ void work_item(const SweepArgs& A, int& tile, int& chunk) {
-  chunk = blockIdx.x / A.ntiles;
-  tile = blockIdx.x % A.ntiles;
+__device__ __forceinline__ void work_item(const SweepArgs& A, int blk, int& tile, int& chunk) {
+  chunk = blk / A.ntiles;
+  tile = blk % A.ntiles;
 }
 
 // Step of stage k (1-based) of a launch.

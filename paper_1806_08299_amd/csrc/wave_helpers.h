@@ -44,4 +44,10 @@ __global__ void k_copy(const float* __restrict__ s, float* __restrict__ d, int64
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) d[i] = s[i];
 }
 
+// out = a - b (the residual of modelled against observed traces).
+__global__ void k_sub(const float* __restrict__ a, const float* __restrict__ b, float* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = a[i] - b[i];
+}
+
 }  // namespace wavett

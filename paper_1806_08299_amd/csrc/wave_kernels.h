@@ -149,8 +149,10 @@ __device__ __forceinline__ void unroll_rot(F&& f, std::integer_sequence<int, Is.
 
 // Thread slot i of (wave w, lane l):  3D: (ly, lx) = (w*RY + i, l);
 // 2D: (0, (w*RY + i)*64 + l).
-template <int R, int DIM, int MODE, int NW, int RY>
-__global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
+template <int R, int DIM, int MODE, int NW, int RY, bool BATCH>
+__global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>::type P) {
+  int blk;
+  const SweepArgs& A = shot_args(P, blk);
   constexpr bool HY = (DIM == 3);
   constexpr int W = 2 * R + 1;
   constexpr bool ROT = W <= kMaxUnrollW;
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   int tile, chunk;
-  work_item(A, tile, chunk);
+  work_item(A, blk, tile, chunk);
   const int ty = tile / A.tiles_x, tx = tile % A.tiles_x;
   const int gy0 = ty * TY, gx0 = tx * TX;
   const int za = chunk * A.zchunk;
@@ -380,8 +382,10 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(SweepArgs A) {
 
 // --------------------------------------------------------------- time-tiled sweep
 
-template <int R, int T, int DIM, int MODE, int NW, int RY>
-__global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
+template <int R, int T, int DIM, int MODE, int NW, int RY, bool BATCH>
+__global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::type P) {
+  int blk;
+  const SweepArgs& A = shot_args(P, blk);
   constexpr bool HY = (DIM == 3);
   constexpr int W = 2 * R + 1;
   constexpr bool ROT = W <= kMaxUnrollW;
@@ -401,7 +405,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(SweepArgs A) {
   const int CY = HY ? EY - 2 * H : 1;
   const int CX = EX - 2 * H;
   int tile, chunk;
-  work_item(A, tile, chunk);
+  work_item(A, blk, tile, chunk);
   const int ty = tile / A.tiles_x, tx = tile % A.tiles_x;
   const int gy0 = ty * CY - HYH, gx0 = tx * CX - H;
   const int za = chunk * A.zchunk;

@@ -18,18 +18,28 @@ BlockShape block_shape(int kind, int dim, int shape);
 // Largest fused depth T instantiated for (radius, dim, shape); 0 if none.
 int tiled_tmax(int R, int dim, int shape);
 
-// Launch one sweep.  `lds_bytes` is the dynamic LDS of the tiled kernel.
+// Launch one sweep of a single context (SweepArgs in the kernel-argument
+// segment at static offsets).  `lds_bytes` is the dynamic LDS of the tiled kernel.
 hipError_t launch_sweep(int R, int kind, int T, int dim, int mode, int shape, const SweepArgs& A,
+                        dim3 grid, size_t lds_bytes, hipStream_t s);
+// Launch one sweep over the shots of B (batched instantiations: untiled, or
+// T <= kBatchTmax).
+hipError_t launch_batch(int R, int kind, int T, int dim, int mode, int shape, const BatchArgs& B,
                         dim3 grid, size_t lds_bytes, hipStream_t s);
 
 // Per-(radius, mode) entry points, one translation unit each.
-#define WAVE_DECL1(RR, MM) \
+#define WAVE_DECL1(RR, MM)                                                                          \
   hipError_t launch_sweep_r##RR##_m##MM(int kind, int T, int dim, int shape, const SweepArgs& A, \
+                                        dim3 grid, size_t lds_bytes, hipStream_t s);              \
+  hipError_t launch_batch_r##RR##_m##MM(int kind, int T, int dim, int shape, const BatchArgs& B, \
                                         dim3 grid, size_t lds_bytes, hipStream_t s);
 #define WAVE_DECL(RR) WAVE_DECL1(RR, 0) WAVE_DECL1(RR, 1) WAVE_DECL1(RR, 2)
 WAVE_DECL(1) WAVE_DECL(2) WAVE_DECL(3) WAVE_DECL(4) WAVE_DECL(5) WAVE_DECL(6) WAVE_DECL(7) WAVE_DECL(8)
 #undef WAVE_DECL
 #undef WAVE_DECL1
+
+// Deepest time tile of the batched instantiations (bounds the build).
+constexpr int kBatchTmax = 2;
 
 // Depth limits per (radius, dim, shape), shared by host planning and the
 // instantiation units.  Bounded by the register file: every fused level keeps

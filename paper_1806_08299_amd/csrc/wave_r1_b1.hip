@@ -1,0 +1,5 @@
+// Batched sweep kernels (untiled, depth <= 2) of stencil radius 1 (space order 2), mode 1 (0 forward, 1 forward storing history, 2 adjoint with imaging).
+#define WAVE_R 1
+#define WAVE_MODE 1
+#define WAVE_BATCH 1
+#include "wave_inst.inc"

@@ -1,4 +1,5 @@
 // Sweep kernels of stencil radius 1 (space order 2), mode 2 (0 forward, 1 forward storing history, 2 adjoint with imaging).
 #define WAVE_R 1
 #define WAVE_MODE 2
+#define WAVE_BATCH 0
 #include "wave_inst.inc"

@@ -1,4 +1,5 @@
 // Sweep kernels of stencil radius 6 (space order 12), mode 0 (0 forward, 1 forward storing history, 2 adjoint with imaging).
 #define WAVE_R 6
 #define WAVE_MODE 0
+#define WAVE_BATCH 0
 #include "wave_inst.inc"

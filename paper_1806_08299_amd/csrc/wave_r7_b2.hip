@@ -1,0 +1,5 @@
+// Batched sweep kernels (untiled, depth <= 2) of stencil radius 7 (space order 14), mode 2 (0 forward, 1 forward storing history, 2 adjoint with imaging).
+#define WAVE_R 7
+#define WAVE_MODE 2
+#define WAVE_BATCH 1
+#include "wave_inst.inc"

@@ -198,6 +198,66 @@ def wave_autotune(ctx, trial_steps, repeats, max_T, scratch):
     return best.value
 
 
+def wave_batch(ctxs, nt, nsrc, src, wavelets, nrec, rec, rec_out, dobs, grad_m, ckpt_every, scratch):
+    """Marshal per-shot lists into the C arrays of wave_batch (lists of equal
+    length; host coordinate arrays float64 [n][ndim], device tensors)."""
+    n = len(ctxs)
+    P = ctypes.c_void_p
+
+    def parr(items):
+        return (P * n)(*[(x.value if isinstance(x, ctypes.c_void_p) else x) for x in items])
+
+    i32a = (ctypes.c_int32 * n)(*[int(v) for v in nsrc])
+    i32b = (ctypes.c_int32 * n)(*[int(v) for v in nrec])
+    sp = parr([_hptr(a) for a in src])
+    rp = parr([_hptr(a) for a in rec])
+    wp = parr([_dptr(t) for t in wavelets])
+    op = parr([_dptr(t) for t in rec_out])
+    dp = parr([_dptr(t) for t in dobs]) if dobs is not None else None
+    gp = parr([_dptr(t) for t in grad_m]) if grad_m is not None else None
+    sc = parr([ctypes.c_void_p(t.data_ptr()) for t in scratch])
+    sb = (ctypes.c_size_t * n)(*[t.numel() * t.element_size() for t in scratch])
+    cp = parr(ctxs)
+    st = lib().wave_batch(cp, n, nt, i32a, sp, wp, i32b, rp, op, dp, gp, ckpt_every, sc, sb)
+    _check(st, ctxs[0])
+
+
+class ShotBatch:
+    """Independent shots (each a WaveOp: own grid, order, model, schedule)
+    advanced together by wave_batch.  Outputs and scratch are kept, so that
+    a repeated run with the same wavelet/observed-data tensors replays the
+    captured graph."""
+
+    def __init__(self, ops, nt, src_xyz, rec_xyz, ckpt_every=0, gradient=False):
+        self.ops = list(ops)
+        self.nt = int(nt)
+        self.src = [_coords(s, op.ndim) for s, op in zip(src_xyz, self.ops)]
+        self.rec = [_coords(r, op.ndim) for r, op in zip(rec_xyz, self.ops)]
+        self.gradient = bool(gradient)
+        self.K = int(ckpt_every) if gradient else 0
+        if self.gradient and self.K < 1:
+            raise ValueError("a gradient batch needs ckpt_every >= 1")
+        dev = self.ops[0].device
+        self.rec_out = [torch.empty((self.nt, r.shape[0]), dtype=torch.float32, device=dev) for r in self.rec]
+        self.grad = [torch.empty(op.shape, dtype=torch.float32, device=dev) for op in self.ops] if gradient else None
+        self.scratch = [
+            torch.empty(max(256, wave_scratch_bytes(op.ctx, self.nt, s.shape[0], r.shape[0], self.K,
+                                                    2 if gradient else 0)), dtype=torch.uint8, device=dev)
+            for op, s, r in zip(self.ops, self.src, self.rec)]
+
+    def run(self, wavelets, dobs=None):
+        wav = [w.to(self.ops[0].device, torch.float32).contiguous() if w.dtype != torch.float32 or not w.is_contiguous()
+               else w for w in wavelets]
+        if self.gradient:
+            if dobs is None:
+                raise ValueError("a gradient batch needs observed traces")
+        else:
+            dobs = None
+        wave_batch([op.ctx for op in self.ops], self.nt, [s.shape[0] for s in self.src], self.src, wav,
+                   [r.shape[0] for r in self.rec], self.rec, self.rec_out, dobs, self.grad, self.K, self.scratch)
+        return self.rec_out, self.grad
+
+
 def wave_tiled_max_depth(space_order: int, ndim: int, tile_shape: int = 1) -> int:
     return int(lib().wave_tiled_max_depth(space_order, ndim, tile_shape))
 
