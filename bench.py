@@ -19,6 +19,8 @@ on one JSON line (progress goes to stderr):
   HBM traffic read from hardware counters when a matching record exists;
 * ai: the arithmetic intensity measured from those counters beside the
   naive and tight estimators of the time-tiling intensity model;
+* batch: 32 independent shots (128^3..320^3, orders 4/8, 800 steps), forward
+  and gradient through one captured sequence, against the shots one by one;
 * cpu_baseline: the FP64 oracle on the host cores on a bounded sample.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
@@ -48,10 +50,13 @@ def log(*a):
 
 
 def kernel_sources_sha() -> str:
-    """Digest of the HIP sources and build script: a counter record is only
-    used while the kernels it measured are unchanged."""
+    """Digest of the sources that define the single-context sweep kernels
+    (kernel templates, per-point arithmetic, instantiation units, build
+    flags): a counter record is only used while they are unchanged."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1806_08299_amd", "csrc", "*")))
+    csrc = os.path.join(ROOT, "paper_1806_08299_amd", "csrc")
+    files = [os.path.join(csrc, f) for f in ("wave_kernels.h", "wave_device.h", "wave_inst.inc")]
+    files += sorted(glob.glob(os.path.join(csrc, "wave_r*_m*.hip")))
     files.append(os.path.join(ROOT, "paper_1806_08299_amd", "build.py"))
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -209,6 +214,91 @@ def gradient_bench(args, dev, stream):
     return out
 
 
+def batch_bench(args, dev, stream):
+    """32 independent shots (128^3..320^3, space orders 4/8, 800 steps):
+    forward and gradient through one captured, merged sequence (wave_batch),
+    against the same shots run one after another."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import ShotBatch, WaveOp
+    from paper_1806_08299_amd.wave import wave_autotune, wave_scratch_bytes
+    if args.quick:
+        S = wi.shot_batch(nshots=6, nt=100, sizes=[(64 + 16 * (i % 3), 64, 80) for i in range(6)], workers=8)
+    else:
+        S = wi.shot_batch(workers=16)
+    nt = S[0].nt
+    K = 40                                   # ~sqrt(2 nt) checkpoints
+    ops, wavs = [], []
+    for w in S:
+        op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
+                    sigma_max=w.sigma_max, time_tile=-1)
+        sc = op.scratch(wave_scratch_bytes(op.ctx, 20, 0, 0, 0, 0))
+        wave_autotune(op.ctx, 20, 1, 2, sc)          # batched kernels: untiled or T <= 2
+        op._scratch = None
+        ops.append(op)
+        wavs.append(torch.from_numpy(w.wavelet).to(dev))
+    npts = sum(w.npts for w in S)
+    scheds = {}
+    for op in ops:
+        key = "T=%d shape=%d" % (op.schedule()[0], op.schedule()[2])
+        scheds[key] = scheds.get(key, 0) + 1
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3, out
+
+    # one after another (single-context calls)
+    def seq_forward():
+        return [op.forward(nt, w.src_xyz, wv, w.rec_xyz)[0] for op, w, wv in zip(ops, S, wavs)]
+    seq_forward()
+    t_seq, recs_seq = timed(seq_forward)
+    dobs = [(0.5 * r).contiguous() for r in recs_seq]
+
+    def seq_grad():
+        out = []
+        for op, w, wv, d in zip(ops, S, wavs, dobs):
+            rec, _ = op.forward(nt, w.src_xyz, wv, w.rec_xyz, ckpt_every=K, adjoint_scratch=True)
+            gm, _ = op.adjoint_grad(nt, w.src_xyz, wv, w.rec_xyz, rec - d, K, want_grad_wavelet=False, reuse=True)
+            op._scratch = None               # release before the next shot
+            torch.cuda.empty_cache()
+            out.append(gm)
+        return out
+    tg_seq, _ = timed(seq_grad)
+    torch.cuda.empty_cache()
+    log("batch: %d shots, %.1f Mpts, sequential forward %.3f s, gradient %.3f s" % (len(S), npts / 1e6, t_seq, tg_seq))
+
+    # batched: first call records and captures, the timed call replays
+    B = ShotBatch(ops, nt, [w.src_xyz for w in S], [w.rec_xyz for w in S])
+    t_first, _ = timed(lambda: B.run(wavs))
+    t_fwd, (recs_b, _) = timed(lambda: B.run(wavs))
+    same_fwd = all(torch.equal(a, b) for a, b in zip(recs_b, recs_seq))
+    del B
+    torch.cuda.empty_cache()
+    G = ShotBatch(ops, nt, [w.src_xyz for w in S], [w.rec_xyz for w in S], ckpt_every=K, gradient=True)
+    tg_first, _ = timed(lambda: G.run(wavs, dobs))
+    tg, (_, grads) = timed(lambda: G.run(wavs, dobs))
+    finite = all(bool(torch.isfinite(g).all().item()) for g in grads)
+    del G
+    torch.cuda.empty_cache()
+    log("batch: batched forward %.3f s (first call %.3f s), gradient %.3f s (first call %.3f s)"
+        % (t_fwd, t_first, tg, tg_first))
+    return {"workload": "shot_batch: %d shots, %d^3..%d^3 grids (%.1f Mpts in all), space orders 4/8, nt=%d, "
+                        "gradient checkpoints every %d" % (len(S), round(min(w.npts for w in S) ** (1 / 3)),
+                                                          round(max(w.npts for w in S) ** (1 / 3)), npts / 1e6, nt, K),
+            "schedules": scheds, "unit": "Gpts/s",
+            "forward": {"value": round(npts * nt / t_fwd / 1e9, 2), "s": round(t_fwd, 4),
+                        "first_call_s": round(t_first, 4), "sequential_value": round(npts * nt / t_seq / 1e9, 2),
+                        "speedup_vs_sequential": round(t_seq / t_fwd, 3), "bitwise_equal_to_sequential": same_fwd},
+            "gradient": {"value": round(npts * nt / tg / 1e9, 2), "s": round(tg, 4), "first_call_s": round(tg_first, 4),
+                         "sequential_value": round(npts * nt / tg_seq / 1e9, 2),
+                         "speedup_vs_sequential": round(tg_seq / tg, 3), "grad_finite": finite}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +313,7 @@ def main():
     ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run plain device copies of known size (reference for the traffic counters)")
     ap.add_argument("--quick", action="store_true", help="small sizes for a functional check")
@@ -329,6 +420,7 @@ def main():
     torch.cuda.empty_cache()
 
     adj = None if args.no_adjoint else gradient_bench(args, dev, stream)
+    batch = None if args.no_batch else batch_bench(args, dev, stream)
     cpu = None if args.no_cpu else cpu_baseline(w)
 
     line = {
@@ -342,6 +434,7 @@ def main():
         "untiled": untiled,
         "speedup_vs_untiled": round(value / untiled["value"], 3) if untiled else None,
         "adjoint_grad": adj,
+        "batch": batch,
         "roofline": roofline,
         "ai": ai,
         "cpu_baseline": cpu,

@@ -188,20 +188,29 @@ def gradient_256(nt: int = 2000, n: int = 256, seed: int = 4, nbl: int = 40, ckp
     return {"true": true, "init": init, "ckpt_every": ckpt_every}
 
 
-def shot_batch(nshots: int = 32, nt: int = 800, seed: int = 5, sizes=None) -> list:
+def shot_batch(nshots: int = 32, nt: int = 800, seed: int = 5, sizes=None, workers: int = 1) -> list:
     """Batch of independent shots: per-axis sizes from {128, 144, ..., 320},
     space order alternating 4/8, per-shot smooth random model, random source
-    (interior, depth >= 2 radius), receiver line at depth 2, no layer."""
+    (interior, depth >= 2 radius), receiver line at depth 2, no layer.  The
+    models are generated on `workers` threads (same result for any count)."""
     rng = np.random.default_rng(seed)
     choices = np.arange(128, 321, 16)
-    out = []
+    spec = []
     for i in range(nshots):
         shp = tuple(int(v) for v in (rng.choice(choices, size=3) if sizes is None else sizes[i]))
         so = 4 if i % 2 == 0 else 8
         r = so // 2
         src = (int(rng.integers(2 * r, shp[0] - 2 * r)), int(rng.integers(2 * r, shp[1] - 2 * r)),
                int(rng.integers(2 * r, shp[2] - 2 * r)))
+        spec.append((shp, so, src))
+
+    def one(i):
+        shp, so, src = spec[i]
         c = smooth_random_velocity(shp, seed * 1000 + i)
-        w = make_workload("batch_shot%02d" % i, shp, 10.0, so, nt, 0, c, 10.0, src, 2, c_max=C_MAX)
-        out.append(w)
-    return out
+        return make_workload("batch_shot%02d" % i, shp, 10.0, so, nt, 0, c, 10.0, src, 2, c_max=C_MAX)
+
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            return list(ex.map(one, range(nshots)))
+    return [one(i) for i in range(nshots)]
