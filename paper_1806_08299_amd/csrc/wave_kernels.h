@@ -510,21 +510,19 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
     // push the freshly loaded plane z0 of level n into window 0
 #pragma unroll
     for (int i = 0; i < RY; ++i) win[0][i][(2 * R + rot) % W] = cin[i];
+    // Wave-uniform properties of every stage's plane, then one variant
+    // (damping x forcing/sampling) for the whole iteration: all T stages form
+    // one straight-line block, so the LDS reads of a stage can be issued
+    // while the previous stage computes.  The damped form is exact where
+    // st == 0, so it serves every stage once one stage needs it.
+    bool any_dmp = false, any_ev = false;
 #pragma unroll
     for (int k = 1; k <= T; ++k) {
       const int zk = z0 - k * R;
-      const bool zin = zk >= 0 && zk < n0;
       const bool zown = zk >= za && zk < zb;
-      const int step = stage_step(A, k);
-      const float* pl = buf + (k - 1) * PL;
-      const float stz = A.has_damp ? damp_term(zk, n0, A.nbl, A.st_coef) : 0.0f;
-      const bool fz = zk >= A.inj_zlo && zk < A.inj_zhi;
-      const bool sz = zown && zk >= A.smp_zlo && zk < A.smp_zhi;
-      const uint32_t so = sg.off(zk, za, zb);   // stores: owned planes only
-      const rsrc_t rh = (MODE != MODE_FWD) ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
-      const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ra;
-      bool dmp = false;
+      any_ev |= (zk >= A.inj_zlo && zk < A.inj_zhi) || (zown && zk >= A.smp_zlo && zk < A.smp_zhi);
       if (A.has_damp) {
+        const float stz = damp_term(zk, n0, A.nbl, A.st_coef);
         bool rows_damped = false;
 #pragma unroll
         for (int i = 0; i < RY; ++i)
@@ -532,12 +530,23 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
         bool lane_damped = stz != 0.0f || rows_damped;
 #pragma unroll
         for (int i = 0; i < (HY ? 1 : RY); ++i) lane_damped |= stx[i] != 0.0f;
-        dmp = wave_any(lane_damped);
+        any_dmp |= wave_any(lane_damped);
       }
-      // Wave-uniform variants keep every row of a stage in one straight-line
-      // block (see the untiled kernel).
-      auto rows = [&](auto dm, auto ev) {
-        constexpr bool DM = decltype(dm)::value, EV = decltype(ev)::value;
+    }
+    auto stages = [&](auto dm, auto ev) {
+      constexpr bool DM = decltype(dm)::value, EV = decltype(ev)::value;
+#pragma unroll
+      for (int k = 1; k <= T; ++k) {
+        const int zk = z0 - k * R;
+        const bool zown = zk >= za && zk < zb;
+        const int step = stage_step(A, k);
+        const float* pl = buf + (k - 1) * PL;
+        const float stz = (DM && A.has_damp) ? damp_term(zk, n0, A.nbl, A.st_coef) : 0.0f;
+        const bool fz = EV && zk >= A.inj_zlo && zk < A.inj_zhi;
+        const bool sz = EV && zown && zk >= A.smp_zlo && zk < A.smp_zhi;
+        const uint32_t so = sg.off(zk, za, zb);   // stores: owned planes only
+        const rsrc_t rh = (MODE != MODE_FWD) ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
+        const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ra;
         float v[RY], st[RY], upv[RY];
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
@@ -594,14 +603,14 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
 #pragma unroll
           for (int i = 0; i < RY; ++i) win[k < T ? k : 0][i][(2 * R + rot) % W] = v[i];
         }
-      };
-      using TT = std::true_type;
-      using FF = std::false_type;
-      if (fz || sz) {
-        if (dmp) rows(TT{}, TT{}); else rows(FF{}, TT{});
-      } else {
-        if (dmp) rows(TT{}, FF{}); else rows(FF{}, FF{});
       }
+    };
+    using TT = std::true_type;
+    using FF = std::false_type;
+    if (any_ev) {
+      if (any_dmp) stages(TT{}, TT{}); else stages(FF{}, TT{});
+    } else {
+      if (any_dmp) stages(TT{}, FF{}); else stages(FF{}, FF{});
     }
     if (NBUF == 1) __syncthreads();
   };
