@@ -103,7 +103,7 @@ def tune_untiled(op, trial_steps=40, repeats=2):
     """Best axis-0 segment count for the untiled sweep (short trials)."""
     import torch
     best = (1e30, 0)
-    for zc in (0, 1, 2, 4, 8, 16, 32):
+    for zc in (0, 1, 2, 4, 8, 12, 16, 24, 32):
         op.set_schedule(-1, 0, 0, zc)
         op.forward(trial_steps)
         torch.cuda.synchronize()

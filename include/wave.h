@@ -179,7 +179,7 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
 /* Autotune the schedule (T, skew, tile shape, zchunks) on this context's
  * model by timing short trial sweeps (minimum of `repeats` trials per
  * candidate): first every depth T <= max_T and tile shape at the default
- * number of axis-0 segments, then 1..32 segments for the three fastest.
+ * number of axis-0 segments, then 1..32 axis-0 segments for the three fastest.
  * Keeps the fastest.  Synchronises; needs scratch for `trial_steps` forward
  * steps without sources. */
 wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,

@@ -664,7 +664,7 @@ namespace wavett {
 
 BlockShape block_shape(int kind, int dim, int shape) {
   if (dim == 2) return {4, 4, 1, 1024};
-  if (kind == KIND_UNTILED) return {4, 4, 16, 64};
+  if (kind == KIND_UNTILED) return {WAVE_UNTILED_NW, WAVE_UNTILED_RY, WAVE_UNTILED_NW * WAVE_UNTILED_RY, 64};
   if (shape == 2) return {8, 4, 32, 64};
   return {8, 8, 64, 64};
 }
@@ -1274,7 +1274,7 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
   Cand bc = timed.empty() ? Cand{oT, os, osh, oz} : timed[0].second;
   // Phase 2: the number of axis-0 segments (grid size against per-workgroup
   // pipeline fill) for the three fastest schedules.
-  const int zcs[6] = {1, 2, 4, 8, 16, 32};
+  const int zcs[8] = {1, 2, 4, 8, 12, 16, 24, 32};
   for (size_t t = 0; t < std::min<size_t>(3, timed.size()); ++t) {
     if (timed[t].first >= 1e300) break;
     for (int z : zcs) {

@@ -13,6 +13,13 @@ enum : int { KIND_UNTILED = 0, KIND_TILED = 1 };
 //   3D tiled, shape 2 8 waves x 4 rows       -> 32 x 64 extended tile (512 threads)
 //   2D (both)         4 waves x 4 segments   -> 1 x 1024 (256 threads)
 struct BlockShape { int nw, ry, ey, ex; };
+// Untiled 3D block: waves x rows per thread (core 16 x 64 by default).
+#ifndef WAVE_UNTILED_NW
+#define WAVE_UNTILED_NW 4
+#endif
+#ifndef WAVE_UNTILED_RY
+#define WAVE_UNTILED_RY 4
+#endif
 BlockShape block_shape(int kind, int dim, int shape);
 
 // Largest fused depth T instantiated for (radius, dim, shape); 0 if none.

@@ -1,8 +1,12 @@
-"""Parity at the benchmark's full size and launch configurations.
+"""Parity at full size: the benchmark's forward workload (512^3 + 40-point
+layer = 592^3, space order 8) in its launch configurations, the largest grid
+and order of the workload list (768^3 + 40 = 848^3 at space order 16, with
+the fast layered model in place of the smooth one: the properties below do
+not depend on the model), and the 256^3 (+40) gradient problem over 2000
+steps.
 
-The 512^3 (+40 layer = 592^3) space-order-8 layered workload is too large
-for the FP64 oracle to follow over many steps, so two properties are checked
-at full size instead:
+These are too large for the FP64 oracle to follow over many steps, so
+properties are checked instead:
 
 * from a seeded random state (which excites every point, the absorbing layer
   and the grid faces), 10 steps of every benchmarked schedule -- the untiled
@@ -13,7 +17,10 @@ at full size instead:
   receiver samples of that step within 1e-5.  One step is ~30 FP32
   operations (2^-24 ~ 6e-8 each, mostly independent) plus FP32 coefficients
   and b, so the expected error is ~1e-7 (measured 6e-8); 1e-6 leaves margin
-  while any wrong term (an O(1) change) fails.
+  while any wrong term (an O(1) change) fails;
+* gradient problem: the FP32 dot-product test <F q, dd> = <q, F^T dd> over
+  2000 steps within 1e-4, and the gradient bitwise independent of the
+  checkpoint interval and of the schedule (untiled vs time-tiled adjoint).
 """
 import numpy as np
 import pytest
@@ -25,9 +32,11 @@ import waveinputs as wi
 pytestmark = pytest.mark.gpu
 
 
-def test_full_size_schedules_and_one_step_against_oracle():
+@pytest.mark.parametrize("n,so", [(512, 8), (768, 16)])
+def test_full_size_schedules_and_one_step_against_oracle(n, so):
     from paper_1806_08299_amd import WaveOp
-    w = wi.layered_512(nt=11)                         # 592^3, so8, nbl 40
+    from paper_1806_08299_amd.wave import wave_tiled_max_depth
+    w = wi.layered_512(nt=11, n=n, so=so)              # n^3 + 40-point layer
     dev = torch.device("cuda")
     op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
                 sigma_max=w.sigma_max, time_tile=-1)
@@ -41,6 +50,8 @@ def test_full_size_schedules_and_one_step_against_oracle():
     torch.cuda.synchronize()
     assert bool(torch.isfinite(fin_u).all())
     for T, shape, zc in ((-1, 1, 0), (1, 1, 0), (1, 2, 0), (2, 2, 0), (2, 1, 4)):
+        if T > wave_tiled_max_depth(so, 3, shape):
+            continue
         print("full size: T=%d shape=%d zchunks=%d" % (T, shape, zc), flush=True)
         op.set_schedule(T, 0, shape, zc)
         rec_t, fin_t = op.forward(nt0, w.src_xyz, wav[:nt0].contiguous(), w.rec_xyz, u_init=u0, want_final=True)
@@ -67,3 +78,32 @@ def test_full_size_schedules_and_one_step_against_oracle():
     assert err <= 1e-6
     r = rec1.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(r - o["rec"]) / np.linalg.norm(o["rec"]) <= 1e-5
+
+
+def test_full_size_gradient_dot_product_and_schedule_independence():
+    from paper_1806_08299_amd import WaveOp
+    w4 = wi.gradient_256()                              # 336^3 with the layer, so8, 2000 steps, K = 50
+    w = w4["init"]
+    dev = torch.device("cuda")
+    op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
+                sigma_max=w.sigma_max, time_tile=-1)
+    rng = np.random.default_rng(11)
+    q = torch.from_numpy(rng.standard_normal((w.nt, 1)).astype(np.float32)).to(dev)
+    dd = torch.from_numpy(rng.standard_normal((w.nt, w.rec_xyz.shape[0])).astype(np.float32)).to(dev)
+    print("gradient: forward", flush=True)
+    rec, _ = op.forward(w.nt, w.src_xyz, q, w.rec_xyz)
+    print("gradient: adjoint", flush=True)
+    gm, gq = op.adjoint_grad(w.nt, w.src_xyz, q, w.rec_xyz, dd, 50)
+    torch.cuda.synchronize()
+    lhs = float((rec.double() * dd.double()).sum())
+    rhs = float((q.double() * gq.double()).sum())
+    print("gradient: dot test %.3e" % (abs(lhs - rhs) / abs(lhs)), flush=True)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-4
+    assert bool(torch.isfinite(gm).all()) and float(gm.abs().max()) > 0
+    for T, shape, K in ((-1, 1, 40), (2, 2, 50), (1, 1, 64)):
+        print("gradient: T=%d shape=%d K=%d" % (T, shape, K), flush=True)
+        op.set_schedule(T, 0, shape, 0)
+        gm2, _ = op.adjoint_grad(w.nt, w.src_xyz, q, w.rec_xyz, dd, K, want_grad_wavelet=False)
+        torch.cuda.synchronize()
+        assert torch.equal(gm2, gm), (T, shape, K)
+        del gm2
