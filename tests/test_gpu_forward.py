@@ -6,7 +6,8 @@
   skew and axis-0 segmentation available for the order (the paper's
   functional-correctness criterion);
 * edge cases: ragged grids smaller than a tile, partial last windows, nt = 0,
-  points on nodes / on the boundary / outside the grid, 2D, every order.
+  points on nodes / on the boundary / outside the grid, 2D, every order, no
+  sources or receivers, grids of a single point, plane or row.
 """
 import numpy as np
 import pytest
@@ -244,3 +245,38 @@ def test_error_paths():
     with pytest.raises(WaveError) as e:
         wave_forward(op.ctx, 4, None, None, None, None, None, None, 0, tiny, 3)
     assert e.value.status == -4                       # WAVE_ENOMEM
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 7, 3), (6, 1, 9), (1, 5), (7, 1)])
+def test_empty_point_sets_and_degenerate_grids(shape):
+    """No sources, no receivers, grids of one point / one plane / one row,
+    from a random initial state: oracle parity and every schedule bitwise."""
+    so, nt = 4, 9
+    nd = len(shape)
+    rng = np.random.default_rng(21)
+    h = (10.0,) * nd
+    m = wi.to_slowness2(rng.uniform(1500, 3000, size=shape))
+    dt = 0.35 * 10.0 / 3000.0
+    u0 = rng.standard_normal((2,) + tuple(shape)).astype(np.float32)
+    w = wi.Workload("degenerate", tuple(shape), h, dt, so, nt, 0, 0.0, m, np.zeros((0, nd)),
+                    np.zeros((nt, 0), np.float32), np.zeros((0, nd)))
+    g = oracle.Grid(shape, h, dt, so)
+    ref = oracle.forward(g, m.astype(np.float64), nt, u_init=u0.astype(np.float64), want_final=True)
+    op = _op(w, time_tile=-1)
+    ui = torch.from_numpy(u0).cuda()
+    rec, fin = op.forward(nt, None, None, None, u_init=ui, want_final=True)
+    torch.cuda.synchronize()
+    assert rec is None
+    fin_u = fin.cpu().numpy()
+    assert rel(fin_u[0], ref["final"][0]) <= TOL and rel(fin_u[1], ref["final"][1]) <= TOL
+    for T, shp in _schedules(2, nd):
+        if not _try_schedule(op, T, shp):
+            continue
+        _, fin_t = op.forward(nt, None, None, None, u_init=ui, want_final=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(fin_t.cpu().numpy(), fin_u), (T, shp)
+    # adjoint with no receivers and no sources: the gradient is exactly zero
+    gm, gq = op.adjoint_grad(nt, None, None, None, torch.zeros((nt, 0), device="cuda"), 4)
+    torch.cuda.synchronize()
+    assert gq is None
+    assert not bool(gm.abs().max() > 0)
