@@ -69,8 +69,10 @@ typedef struct wave_desc {
   double dt;             /* seconds */
   int32_t nbl;           /* absorbing-layer width in points; 0 = no damping */
   double sigma_max;      /* damping maximum in 1/s (ignored if nbl == 0) */
-  int32_t time_tile;     /* T >= 1 fused steps per launch; 0 = autotune at init;
-                            -1 = untiled single-step sweep (the reference schedule) */
+  int32_t time_tile;     /* T >= 1 fused steps per launch; -1 = untiled single-step
+                            sweep (the reference schedule); 0 = default: T = 2 on
+                            64x64 tiles at radius <= 2 in 3D, untiled otherwise (the
+                            measured best on MI355X; wave_autotune refines by timing) */
   int32_t skew;          /* halo per fused step on the tiled axes; 0 = r; must be >= r */
   int32_t tile_shape;    /* 3D tiled sweep: 0 = auto; 1 = 64x64 extended tile;
                             2 = 32x64 extended tile (both 512 threads).  2D: ignored */
@@ -85,8 +87,8 @@ size_t wave_state_bytes(const wave_desc* d);
 /* Validate `d`, build the schedule and the per-axis damping tables, and derive
  * b = dt^2/m from the model m_dev [N] (s^2/m^2, device, must stay > 0).  The
  * CFL check uses max velocity 1/sqrt(min m): this call synchronises the
- * stream once.  time_tile == 0 runs the autotuner here (synchronising, several
- * trial sweeps).  state_dev must hold wave_state_bytes(d) bytes.
+ * stream once.  time_tile == 0 picks the default schedule (see wave_desc);
+ * wave_autotune measures.  state_dev must hold wave_state_bytes(d) bytes.
  * Errors: WAVE_EINVAL, WAVE_ESKEW, WAVE_ECFL, WAVE_ENOMEM, WAVE_EUNSUPPORTED, WAVE_EHIP. */
 wave_status wave_init(const wave_desc* d, const float* m_dev, void* state_dev, size_t state_bytes,
                       void* hip_stream, wave_ctx** out);

@@ -35,17 +35,18 @@ def sources():
     return srcs
 
 
-def _headers():
+def _headers(with_abi: bool):
     hs = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".h", ".inc"))]
-    inc = os.path.join(ROOT, "include")
-    hs += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
+    if with_abi:   # only the host unit includes the public header
+        inc = os.path.join(ROOT, "include")
+        hs += [os.path.join(inc, f) for f in os.listdir(inc) if f.endswith(".h")]
     return hs
 
 
 def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if incremental and os.path.exists(obj):
-        newest = max(os.path.getmtime(f) for f in _headers() + [src, __file__])
+        newest = max(os.path.getmtime(f) for f in _headers(src.endswith(".cpp")) + [src, __file__])
         if os.path.getmtime(obj) > newest:
             return obj
     cmd = [HIPCC, "-c", "-x", "hip", src, "-o", obj] + FLAGS

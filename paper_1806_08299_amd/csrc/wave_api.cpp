@@ -872,14 +872,18 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
     return s;
   }
   if (T0 == -2) {
-    // default heuristic pick; wave_autotune refines it by measurement
+    // Default schedule from measurements on MI355X (592^3, layered model):
+    // depth 2 on 64 x 64 tiles wins at radius <= 2 in 3D; at larger radii the
+    // halo recomputed by every fused step costs more than the traffic it
+    // saves, so the untiled sweep is the default.  wave_autotune refines by
+    // timing on the actual problem.
     int best = -1;
-    for (int T = std::min(4, tiled_tmax(c->R, c->dim, c->shape)); T >= 2; --T) {
+    if (c->dim == 3 && c->R <= 2) {
+      const int oshape = c->shape;
+      if (d->tile_shape == 0) c->shape = 1;
       Plan pl;
-      if (make_plan(c, KIND_TILED, T, pl) == WAVE_OK) {
-        best = T;
-        break;
-      }
+      if (make_plan(c, KIND_TILED, 2, pl) == WAVE_OK) best = 2;
+      else c->shape = oshape;
     }
     c->T = best;
     c->err.clear();

@@ -280,3 +280,19 @@ def test_empty_point_sets_and_degenerate_grids(shape):
     torch.cuda.synchronize()
     assert gq is None
     assert not bool(gm.abs().max() > 0)
+
+
+@pytest.mark.parametrize("so,shape,expect", [(4, (40, 70, 80), 2), (8, (40, 70, 80), -1), (4, (50, 300), -1)])
+def test_default_schedule(so, shape, expect):
+    """time_tile = 0: depth 2 on 64x64 tiles at radius <= 2 in 3D, untiled
+    otherwise; the result is bitwise that of the untiled sweep."""
+    w = _small(so, shape, nbl=3, seed=31, nt=10)
+    op = _op(w, time_tile=0)
+    T, skew, tshape, _ = op.schedule()
+    assert T == expect and skew == so // 2
+    if T > 0:
+        assert tshape == 1
+    rec_d, fin_d = _run(op, w)
+    op.set_schedule(-1, 0, 0, 0)
+    rec_u, fin_u = _run(op, w)
+    assert np.array_equal(fin_d, fin_u) and np.array_equal(rec_d, rec_u)
