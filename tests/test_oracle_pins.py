@@ -353,3 +353,23 @@ def test_checkpoint_resume_bitwise(oracle_lib):
     b = oracle.forward(g, m, nt - k, src, q[k:], rec, u_init=a["final"], want_final=True)
     assert np.array_equal(np.vstack([a["rec"], b["rec"]]), full["rec"])
     assert np.array_equal(b["final"], full["final"])
+
+
+def test_damping_profile_hand_values(oracle_lib):
+    """sigma at listed points against values worked out by hand from the
+    definition (tests/golden/damping_profile_values.txt)."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "damping_profile_values.txt")
+    n = 0
+    for line in open(path):
+        if not line.strip() or line.startswith("#"):
+            continue
+        f = line.split()
+        nd = int(f[0])
+        shape = tuple(int(v) for v in f[1:1 + nd])
+        nbl, smax = int(f[1 + nd]), float(f[2 + nd])
+        idx = tuple(int(v) for v in f[3 + nd:3 + 2 * nd])
+        expect = float(f[3 + 2 * nd])
+        g = oracle.Grid(shape, (10.0,) * nd, 1e-4, 2, nbl=nbl, sigma_max=smax)
+        assert oracle.sigma(g)[idx] == expect, (shape, nbl, idx)
+        n += 1
+    assert n == 19
