@@ -21,6 +21,8 @@ on one JSON line (progress goes to stderr):
   naive and tight estimators of the time-tiling intensity model;
 * batch: 32 independent shots (128^3..320^3, orders 4/8, 800 steps), forward
   and gradient through one captured sequence, against the shots one by one;
+* tiling_by_order: the best time-tiled against the best untiled schedule on
+  the same 592^3 layered workload at space orders 2, 4 and 8 (100 steps);
 * cpu_baseline: the FP64 oracle on the host cores on a bounded sample.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
@@ -299,6 +301,38 @@ def batch_bench(args, dev, stream):
                          "speedup_vs_sequential": round(tg_seq / tg, 3), "grad_finite": finite}}
 
 
+def tiling_factor(so, dev, stream, nt=100, n=512):
+    """Best untiled and best time-tiled schedule for the layered workload at
+    space order `so` (short runs, minimum of 2), and their ratio."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import WaveOp, WaveError
+    from paper_1806_08299_amd.wave import wave_tiled_max_depth
+    w = wi.layered_512(nt=nt, n=n, so=so)
+    op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
+                sigma_max=w.sigma_max, time_tile=-1)
+    wav = torch.from_numpy(w.wavelet).to(dev)
+
+    def rate(sched):
+        try:
+            op.set_schedule(*sched)
+        except WaveError:
+            return 0.0
+        op.forward(nt, w.src_xyz, wav, w.rec_xyz)
+        t, _ = run_steps(op, w, wav, 1, stream)
+        t = min(t, run_steps(op, w, wav, 1, stream)[0])
+        return w.npts * nt / t / 1e9
+
+    untiled = max((rate((-1, 0, 1, zc)), zc) for zc in (12, 16, 24))
+    tiled = max((rate((T, 0, shape, zc)), (T, shape, zc)) for shape in (1, 2)
+                for T in range(1, wave_tiled_max_depth(so, 3, shape) + 1) for zc in (0, 16, 32))
+    del op
+    torch.cuda.empty_cache()
+    return {"space_order": so, "untiled": round(untiled[0], 1), "untiled_zchunks": untiled[1],
+            "tiled": round(tiled[0], 1), "tiled_schedule": dict(zip(("T", "tile_shape", "zchunks"), tiled[1])),
+            "factor": round(tiled[0] / untiled[0], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +348,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-orders", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run plain device copies of known size (reference for the traffic counters)")
     ap.add_argument("--quick", action="store_true", help="small sizes for a functional check")
@@ -421,6 +456,13 @@ def main():
 
     adj = None if args.no_adjoint else gradient_bench(args, dev, stream)
     batch = None if args.no_batch else batch_bench(args, dev, stream)
+    orders = None
+    if not args.no_orders:
+        orders = []
+        for so in (2, 4, 8):
+            orders.append(tiling_factor(so, dev, stream, n=128 if args.quick else 512))
+            log("order %d: untiled %.1f, tiled %.1f %s -> %.3fx" % (so, orders[-1]["untiled"], orders[-1]["tiled"],
+                                                                  orders[-1]["tiled_schedule"], orders[-1]["factor"]))
     cpu = None if args.no_cpu else cpu_baseline(w)
 
     line = {
@@ -435,6 +477,7 @@ def main():
         "speedup_vs_untiled": round(value / untiled["value"], 3) if untiled else None,
         "adjoint_grad": adj,
         "batch": batch,
+        "tiling_by_order": orders,
         "roofline": roofline,
         "ai": ai,
         "cpu_baseline": cpu,

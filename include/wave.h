@@ -71,7 +71,7 @@ typedef struct wave_desc {
   double sigma_max;      /* damping maximum in 1/s (ignored if nbl == 0) */
   int32_t time_tile;     /* T >= 1 fused steps per launch; -1 = untiled single-step
                             sweep (the reference schedule); 0 = default: T = 2 on
-                            64x64 tiles at radius <= 2 in 3D, untiled otherwise (the
+                            64x64 tiles at radius 1 in 3D, untiled otherwise (the
                             measured best on MI355X; wave_autotune refines by timing) */
   int32_t skew;          /* halo per fused step on the tiled axes; 0 = r; must be >= r */
   int32_t tile_shape;    /* 3D tiled sweep: 0 = auto; 1 = 64x64 extended tile;
@@ -181,7 +181,7 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
 /* Autotune the schedule (T, skew, tile shape, zchunks) on this context's
  * model by timing short trial sweeps (minimum of `repeats` trials per
  * candidate): first every depth T <= max_T and tile shape at the default
- * number of axis-0 segments, then 1..32 axis-0 segments for the three fastest.
+ * number of axis-0 segments, then 1..32 axis-0 segments for the five fastest.
  * Keeps the fastest.  Synchronises; needs scratch for `trial_steps` forward
  * steps without sources. */
 wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,

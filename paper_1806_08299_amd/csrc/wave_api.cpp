@@ -873,12 +873,12 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
   }
   if (T0 == -2) {
     // Default schedule from measurements on MI355X (592^3, layered model):
-    // depth 2 on 64 x 64 tiles wins at radius <= 2 in 3D; at larger radii the
-    // halo recomputed by every fused step costs more than the traffic it
-    // saves, so the untiled sweep is the default.  wave_autotune refines by
-    // timing on the actual problem.
+    // depth 2 on 64 x 64 tiles wins at radius 1 in 3D (1.15x); from radius 2
+    // on the halo recomputed by every fused step costs as much or more than
+    // the traffic it saves, so the untiled sweep is the default.
+    // wave_autotune refines by timing on the actual problem.
     int best = -1;
-    if (c->dim == 3 && c->R <= 2) {
+    if (c->dim == 3 && c->R <= 1) {
       const int oshape = c->shape;
       if (d->tile_shape == 0) c->shape = 1;
       Plan pl;
@@ -1277,9 +1277,11 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
   double best_t = timed.empty() ? 1e300 : timed[0].first;
   Cand bc = timed.empty() ? Cand{oT, os, osh, oz} : timed[0].second;
   // Phase 2: the number of axis-0 segments (grid size against per-workgroup
-  // pipeline fill) for the three fastest schedules.
+  // pipeline fill) for the five fastest schedules: at low orders a time-tiled
+  // schedule that phase 1 ranks behind the untiled sweep can overtake it
+  // with more segments.
   const int zcs[8] = {1, 2, 4, 8, 12, 16, 24, 32};
-  for (size_t t = 0; t < std::min<size_t>(3, timed.size()); ++t) {
+  for (size_t t = 0; t < std::min<size_t>(5, timed.size()); ++t) {
     if (timed[t].first >= 1e300) break;
     for (int z : zcs) {
       if (z > c->n0) break;

@@ -282,9 +282,10 @@ def test_empty_point_sets_and_degenerate_grids(shape):
     assert not bool(gm.abs().max() > 0)
 
 
-@pytest.mark.parametrize("so,shape,expect", [(4, (40, 70, 80), 2), (8, (40, 70, 80), -1), (4, (50, 300), -1)])
+@pytest.mark.parametrize("so,shape,expect", [(2, (40, 70, 80), 2), (4, (40, 70, 80), -1), (8, (40, 70, 80), -1),
+                                               (2, (50, 300), -1)])
 def test_default_schedule(so, shape, expect):
-    """time_tile = 0: depth 2 on 64x64 tiles at radius <= 2 in 3D, untiled
+    """time_tile = 0: depth 2 on 64x64 tiles at radius 1 in 3D, untiled
     otherwise; the result is bitwise that of the untiled sweep."""
     w = _small(so, shape, nbl=3, seed=31, nt=10)
     op = _op(w, time_tile=0)
