@@ -118,30 +118,95 @@ __device__ __forceinline__ void plane_points(const PointSet& ps, int z, int& p0,
   p1 = cload(ps.zptr, z + 1);
 }
 
-// Forcing value at (z, y, x) for `step` (0 where the point is not forced).
-__device__ __forceinline__ float forcing_at(const SweepArgs& A, int z, int y, int x, int step) {
+// Points of plane z in the 64-column window [xw, xw + 64) of row y (all
+// arguments wave-uniform): [a, b).  Within a plane the points are sorted by
+// (y, x), so two binary searches (scalar loads) find the window and at most
+// 64 points remain to compare per lane, however many points the plane holds.
+// The window is clipped to the row, so that it never reaches into row y - 1
+// or y + 1 (whose points would otherwise match a lane's x).
+struct PtRange { int a, b; };
+__device__ __forceinline__ PtRange window_points(const PointSet& ps, int z, int y, int xw, int n2) {
+  int p0, p1;
+  plane_points(ps, z, p0, p1);
+  const int xlo = min(max(xw, 0), n2), xhi = max(min(max(xw + 64, 0), n2), xlo);
+  const int64_t klo = (int64_t)y * n2 + xlo, khi = (int64_t)y * n2 + xhi;
+  auto key = [&](int p) { return (int64_t)cload(ps.y, p) * n2 + cload(ps.x, p); };
+  int lo = p0, hi = p1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (key(mid) < klo) lo = mid + 1; else hi = mid;
+  }
+  const int a = lo;
+  hi = p1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (key(mid) < khi) lo = mid + 1; else hi = mid;
+  }
+  return PtRange{a, lo};
+}
+
+// Forcing value at (z, y, x) for `step` (0 where the point is not forced);
+// x lies in the window [xw, xw + 64).
+__device__ __forceinline__ float forcing_at(const SweepArgs& A, int z, int y, int xw, int x, int step) {
   const SweepAux* X = opaque(A.aux);
   const PointSet ps{cload(&X->inj.zptr, 0), cload(&X->inj.y, 0), cload(&X->inj.x, 0), cload(&X->inj.npts, 0)};
   const float* tab = cload(&X->inj_table, 0);
-  int p0, p1;
-  plane_points(ps, z, p0, p1);
+  const PtRange w = window_points(ps, z, y, xw, A.n2);
   float f = 0.0f;
-  for (int p = p0; p < p1; ++p) {
+  for (int p = w.a; p < w.b; ++p) {
     const float v = cload(tab, (int64_t)step * ps.npts + p);
-    if (cload(ps.y, p) == y && cload(ps.x, p) == x) f = v;
+    if (cload(ps.x, p) == x) f = v;
   }
   return f;
 }
 
-// Record v at (z, y, x) for `step` if that point is sampled.
-__device__ __forceinline__ void sample_at(const SweepArgs& A, int z, int y, int x, int step, float v) {
+// Record v at (z, y, x) for `step` if that point is sampled; x lies in the
+// window [xw, xw + 64).
+__device__ __forceinline__ void sample_at(const SweepArgs& A, int z, int y, int xw, int x, int step, float v) {
   const SweepAux* X = opaque(A.aux);
   const PointSet ps{cload(&X->smp.zptr, 0), cload(&X->smp.y, 0), cload(&X->smp.x, 0), cload(&X->smp.npts, 0)};
   float* out = cload(&X->smp_out, 0);
-  int p0, p1;
-  plane_points(ps, z, p0, p1);
-  for (int p = p0; p < p1; ++p)
-    if (cload(ps.y, p) == y && cload(ps.x, p) == x) out[(int64_t)step * ps.npts + p] = v;
+  const PtRange w = window_points(ps, z, y, xw, A.n2);
+  for (int p = w.a; p < w.b; ++p)
+    if (cload(ps.x, p) == x) out[(int64_t)step * ps.npts + p] = v;
+}
+
+// The forcing values / samples of a thread's RY rows.  Row r lies at
+// y = ybase + r, window xw = xbase (3D), or y = ybase, xw = xbase + 64 r (2D).
+// The rows are visited in a loop that is not unrolled, each result reaching
+// its row's register through uniform selects: one lookup is live at a time
+// and its code exists once, whatever RY, T and the variant.
+template <int RY, bool HY>
+__device__ __forceinline__ void forcing_rows(const SweepArgs& A, int z, int ybase, int xbase, int lane, int step,
+                                             float (&f)[RY]) {
+#pragma unroll
+  for (int i = 0; i < RY; ++i) f[i] = 0.0f;
+#pragma unroll 1
+  for (int r = 0; r < RY; ++r) {
+    const int y = HY ? ybase + r : ybase, xw = HY ? xbase : xbase + 64 * r;
+    const float v = forcing_at(A, z, y, xw, xw + lane, step);
+#pragma unroll
+    for (int i = 0; i < RY; ++i) f[i] = (i == r) ? v : f[i];
+  }
+}
+
+template <int RY, bool HY, typename Keep>
+__device__ __forceinline__ void sample_rows(const SweepArgs& A, int z, int ybase, int xbase, int lane, int step,
+                                            const float (&v)[RY], Keep keep) {
+#pragma unroll 1
+  for (int r = 0; r < RY; ++r) {
+    float vr = 0.0f;
+    bool kr = false;
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+      vr = (i == r) ? v[i] : vr;
+      kr = (i == r) ? keep(i) : kr;
+    }
+    if (kr) {
+      const int y = HY ? ybase + r : ybase, xw = HY ? xbase : xbase + 64 * r;
+      sample_at(A, z, y, xw, xw + lane, step, vr);
+    }
+  }
 }
 
 // Whole-wave "any lane" test (uniform result).
@@ -313,7 +378,9 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
     }
     auto rows = [&](auto dm, auto ev) {
       constexpr bool DM = decltype(dm)::value, EV = decltype(ev)::value;
-      float v[RY], st[RY];
+      float v[RY], st[RY], fr[RY];
+      const int ybase = gy0 + (HY ? wv * RY : 0), xbase = gx0 + (HY ? 0 : wv * RY * 64);
+      if (EV && fz) forcing_rows<RY, HY>(A, z, ybase, xbase, lane, step, fr);
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
         float zm[R], zp[R], ym[R], yp[R], xm[R], xp[R];
@@ -329,11 +396,7 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
             yp[j - 1] = (i + j < RY) ? zw[(i + j < RY) ? i + j : 0][(R + rot) % W] : row[j * LDW];
           }
         }
-        float f = 0.0f;
-        if (EV && fz) {
-          const int ly = HY ? wv * RY + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
-          f = forcing_at(A, z, gy0 + ly, gx0 + lx, step);
-        }
+        const float f = (EV && fz) ? fr[i] : 0.0f;
         st[i] = 0.0f;
         if (DM) {
           const float sty = HY ? damp_term(gy0 + wv * RY + i, A.n1, A.nbl, A.st_coef) : 0.0f;
@@ -347,10 +410,6 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
       for (int i = 0; i < RY; ++i) {
         const uint32_t o = col[i];
         bstore(ro, o, so, v[i]);
-        if (EV && sz && o != kOOB) {
-          const int ly = HY ? wv * RY + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
-          sample_at(A, z, gy0 + ly, gx0 + lx, step, v[i]);
-        }
         if (MODE == MODE_HIST) {
           bstore(rh, o, so, v[i]);
         } else if (MODE == MODE_ADJ) {
@@ -358,6 +417,7 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
           bstore(rg, o, so, image_step(bload(rg, o, so), u, st[i], v[i], zw[i][(R + rot) % W], up[i]));
         }
       }
+      if (EV && sz) sample_rows<RY, HY>(A, z, ybase, xbase, lane, step, v, [&](int i) { return col[i] != kOOB; });
     };
     using TT = std::true_type;
     using FF = std::false_type;
@@ -554,7 +614,9 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
         const uint32_t so = sg.off(zk, za, zb);   // stores: owned planes only
         const rsrc_t rh = (MODE != MODE_FWD) ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
         const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ra;
-        float v[RY], st[RY], upv[RY];
+        float v[RY], st[RY], upv[RY], fr[RY];
+        const int ybase = gy0 + (HY ? wrow0 : 0), xbase = gx0 + (HY ? 0 : wv * RY * 64);
+        if (EV && fz) forcing_rows<RY, HY>(A, zk, ybase, xbase, lane, step, fr);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
           float zm[R], zp[R], ym[R], yp[R], xm[R], xp[R];
@@ -571,11 +633,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
             }
           }
           upv[i] = (k == 1) ? pin[i] : win[(k >= 2) ? k - 2 : 0][i][rot % W];
-          float f = 0.0f;
-          if (EV && fz) {
-            const int ly = HY ? wrow0 + i : 0, lx = HY ? lane : (wv * RY + i) * 64 + lane;
-            f = forcing_at(A, zk, gy0 + ly, gx0 + lx, step);
-          }
+          const float f = (EV && fz) ? fr[i] : 0.0f;
           st[i] = 0.0f;
           if (DM) {
             const float sty = HY ? damp_term(gy0 + wrow0 + i, A.n1, A.nbl, A.st_coef) : 0.0f;
@@ -585,16 +643,15 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
                                  bin[k - 1][i], st[i], f, DM, EV && fz);
           if (DM) v[i] = wave_damp(v[i], st[i]);
         }
-#pragma unroll
-        for (int i = 0; i < RY; ++i) {
-          // in range only for core points of owned planes
+        // in range only for core points of owned planes
+        auto outoff = [&](int i) {
           const int ly = HY ? wrow0 + i : 0;
           const bool rcore = !HY || (ly >= HYH && ly < HYH + CY);
-          const uint32_t o = (rcore && xcore[HY ? 0 : i]) ? col[i] : kOOB;
-          if (EV && sz && o != kOOB) {
-            const int lx = HY ? lane : (wv * RY + i) * 64 + lane;
-            sample_at(A, zk, gy0 + ly, gx0 + lx, step, v[i]);
-          }
+          return (rcore && xcore[HY ? 0 : i]) ? col[i] : kOOB;
+        };
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+          const uint32_t o = outoff(i);
           if (MODE == MODE_HIST) {
             bstore(rh, o, so, v[i]);
           } else if (MODE == MODE_ADJ) {
@@ -606,6 +663,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
             bstore(rB, o, so, win[k - 1][i][(R + rot) % W]);
           }
         }
+        if (EV && sz) sample_rows<RY, HY>(A, zk, ybase, xbase, lane, step, v, [&](int i) { return outoff(i) != kOOB; });
         if (k < T) {
 #pragma unroll
           for (int i = 0; i < RY; ++i) win[k < T ? k : 0][i][(2 * R + rot) % W] = v[i];
