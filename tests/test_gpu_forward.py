@@ -297,3 +297,39 @@ def test_default_schedule(so, shape, expect):
     op.set_schedule(-1, 0, 0, 0)
     rec_u, fin_u = _run(op, w)
     assert np.array_equal(fin_d, fin_u) and np.array_equal(rec_d, rec_u)
+
+
+@pytest.mark.parametrize("shape", [(20, 9, 47), (16, 6, 130), (30, 700)])
+def test_dense_receiver_lines_on_adjacent_rows(shape):
+    """Receivers on every node of two adjacent rows and sources on a third,
+    in rows shorter and longer than one 64-lane window: each trace against
+    the oracle and every schedule bitwise (the per-window point lookup must
+    never take a point of a neighbouring row)."""
+    nd = len(shape)
+    so, nt = 4, 14
+    rng = np.random.default_rng(41)
+    h = (10.0,) * nd
+    m = wi.to_slowness2(rng.uniform(1500, 3000, size=shape))
+    dt = 0.35 * 10.0 / 3000.0
+    n2 = shape[-1]
+    if nd == 3:
+        z, y = shape[0] // 2, shape[1] // 2
+        rec = [[z * h[0], yy * h[1], x * h[2]] for yy in (y - 1, y) for x in range(n2)]
+        src = [[z * h[0], (y + 1) * h[1], x * h[2]] for x in range(0, n2, 5)]
+    else:
+        z = shape[0] // 2
+        rec = [[zz * h[0], x * h[1]] for zz in (z - 1, z) for x in range(n2)]
+        src = [[(z + 1) * h[0], x * h[1]] for x in range(0, n2, 7)]
+    src, rec = np.array(src), np.array(rec)
+    wav = rng.standard_normal((nt, len(src))).astype(np.float32)
+    w = wi.Workload("lines", tuple(shape), h, dt, so, nt, 0, 0.0, m, src, wav, rec)
+    ref = _oracle(w)
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    assert rel(fin_u[0], ref["final"][0]) <= TOL
+    assert rel(rec_u, ref["rec"]) <= TOL
+    for T, shp in _schedules(2, nd):
+        if not _try_schedule(op, T, shp):
+            continue
+        rec_t, fin_t = _run(op, w)
+        assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u), (T, shp)
