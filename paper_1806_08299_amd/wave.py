@@ -387,18 +387,27 @@ class WaveFn(torch.autograd.Function):
         op.set_model(m.detach())
         nt = wavelet.shape[0]
         rec, _ = op.forward(nt, src_xyz, wavelet.detach(), rec_xyz, ckpt_every=ckpt_every, adjoint_scratch=True)
+        # The checkpoints left in the op's scratch belong to this forward only
+        # while no other forward has run on the op since.
+        token = object()
+        op._fwd_token = token
+        ctx.token = token
         ctx.op = op
         ctx.src_xyz = src_xyz
         ctx.rec_xyz = rec_xyz
         ctx.ckpt_every = ckpt_every
-        ctx.save_for_backward(wavelet.detach())
+        ctx.save_for_backward(m.detach(), wavelet.detach())
         return rec
 
     @staticmethod
     def backward(ctx, grad_rec):
-        (wavelet,) = ctx.saved_tensors
+        m, wavelet = ctx.saved_tensors
         op = ctx.op
         nt = wavelet.shape[0]
+        reuse = getattr(op, "_fwd_token", None) is ctx.token
+        if not reuse:                      # another forward ran on the op: its model and checkpoints are not ours
+            op.set_model(m)
         gm, gq = op.adjoint_grad(nt, ctx.src_xyz, wavelet, ctx.rec_xyz, grad_rec.contiguous(), ctx.ckpt_every,
-                                 want_grad_wavelet=ctx.needs_input_grad[1], reuse=True)
+                                 want_grad_wavelet=ctx.needs_input_grad[1], reuse=reuse)
+        op._fwd_token = None               # adjoint_grad overwrote the scratch
         return gm, gq, None, None, None, None

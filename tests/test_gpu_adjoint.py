@@ -167,3 +167,31 @@ def test_gradient_2d_every_order():
         op.set_schedule(2, 0, 0, 0)
         gm_t, gq_t = _grad(op, P, K=7)
         assert np.array_equal(gm_t, gm_u) and np.array_equal(gq_t, gq_u), so
+
+
+def test_autograd_interleaved_forwards(prob):
+    """Two forwards on one op with different models, then the backward of the
+    first: its gradient must be that of a lone forward/backward with the first
+    model (the checkpoints of the second forward must not be reused)."""
+    from paper_1806_08299_amd import WaveFn
+    op = _op(prob, prob["m0"], time_tile=2)
+    wav = torch.from_numpy(prob["wav"]).cuda()
+    dobs = torch.from_numpy(prob["dobs"].astype(np.float32)).cuda()
+
+    def loss_of(m):
+        r = WaveFn.apply(m, wav, op, prob["src"], prob["rec"], 10)
+        return 0.5 * ((r - dobs) ** 2).sum()
+
+    m1 = torch.from_numpy(prob["m0"]).cuda().requires_grad_(True)
+    loss_of(m1).backward()
+    ref = m1.grad.clone()
+    m1.grad = None
+    m2 = torch.from_numpy((prob["m0"] * 1.05).astype(np.float32)).cuda().requires_grad_(True)
+    l1 = loss_of(m1)
+    l2 = loss_of(m2)
+    l1.backward()
+    assert torch.equal(m1.grad, ref)
+    l2.backward()
+    m3 = m2.detach().clone().requires_grad_(True)
+    loss_of(m3).backward()
+    assert torch.equal(m2.grad, m3.grad)
