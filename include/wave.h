@@ -136,7 +136,10 @@ wave_status wave_forward(wave_ctx* ctx, int32_t nt,
  *                   keeps the whole history)
  *   reuse           1: use the checkpoints of the immediately preceding
  *                   wave_forward on this context and scratch (same nt, K,
- *                   geometry; else WAVE_ESTATE); 0: run that forward here.
+ *                   sources and wavelet buffer, model unchanged since:
+ *                   wave_set_model and every other sweep discard them; else
+ *                   WAVE_ESTATE); the wavelet's contents must not have
+ *                   changed either; 0: run that forward here.
  * Forward segments are recomputed from checkpoints with the time-tiled
  * kernel (storing their history), then swept backwards with the time-tiled
  * adjoint kernel that accumulates the imaging condition. */

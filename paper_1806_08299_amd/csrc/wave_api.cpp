@@ -62,6 +62,7 @@ struct wave_ctx {
     bool valid = false;
     int nt = 0, K = 0, nsrc = 0, nrec = 0;
     const void* scratch = nullptr;
+    const float* wavelet = nullptr;
     std::vector<double> src, rec;
   } ck;
   SweepAux aux_host[4];          // sources of the per-call table copies
@@ -930,6 +931,7 @@ wave_status wave_forward(wave_ctx* c, int32_t nt, int32_t nsrc, const double* sr
     c->ck.nsrc = nsrc;
     c->ck.nrec = nrec;
     c->ck.scratch = scratch;
+    c->ck.wavelet = wav;
     c->ck.src.assign(src, src + (size_t)nsrc * c->dim);
   }
   return WAVE_OK;
@@ -1039,6 +1041,7 @@ wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const doubl
   char* sc = (char*)scratch;
   if (reuse) {
     const bool ok = c->ck.valid && c->ck.nt == nt && c->ck.K == K && c->ck.nsrc == nsrc && c->ck.scratch == scratch &&
+                    c->ck.wavelet == wav &&
                     std::equal(c->ck.src.begin(), c->ck.src.end(), src);
     if (!ok) return fail(c, WAVE_ESTATE, "no matching checkpoints from a preceding forward");
   }
@@ -1240,6 +1243,7 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
   const Layout L = layout(c, trial_steps, 0, 0, 0, 0);
   if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
   c->gen++;
+  c->ck.valid = false;   // the trial sweeps overwrite the state (and perhaps the scratch)
   struct Cand { int T, skew, shape, zc; };
   std::vector<Cand> cands;
   cands.push_back({-1, c->R, c->shape ? c->shape : 1, 0});
