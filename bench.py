@@ -133,9 +133,35 @@ def kernel_name(sched, so) -> str:
     return "k_tiled R=%d T=%d tile_shape=%d" % (so // 2, T, shape)
 
 
-def cpu_baseline(w, budget_s=20.0):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE_ONE_THREAD = r"""
+import sys, time, json
+sys.path.insert(0, sys.argv[1])
+import numpy as np, oracle, waveinputs as wi
+w = wi.layered_512(nt=1, n=int(sys.argv[2]))
+g = oracle.Grid(w.shape, w.spacing, w.dt, w.so, nbl=w.nbl, sigma_max=w.sigma_max)
+m = w.m.astype(np.float64)
+t0 = time.perf_counter()
+oracle.forward(g, m, 1, w.src_xyz, w.wavelet[:1].astype(np.float64), w.rec_xyz)
+print(json.dumps({"s": time.perf_counter() - t0, "npts": int(w.npts)}))
+"""
+
+
+def cpu_baseline(w, budget_s=20.0, n=512):
     """FP64 oracle on the host: the same grid, model, order and source for a
-    few time steps (bounded to ~budget_s of CPU work), as Gpts/s."""
+    few time steps (bounded to ~budget_s of CPU work), as Gpts/s, on all the
+    threads OpenMP is given; plus one step on one thread (a child process
+    with OMP_NUM_THREADS=1)."""
+    import subprocess
     import oracle
     oracle.build(force=False)
     g = oracle.Grid(w.shape, w.spacing, w.dt, w.so, nbl=w.nbl, sigma_max=w.sigma_max)
@@ -148,9 +174,21 @@ def cpu_baseline(w, budget_s=20.0):
     t0 = time.perf_counter()
     oracle.forward(g, m, steps, w.src_xyz, w.wavelet[:steps].astype(np.float64), w.rec_xyz)
     dt = time.perf_counter() - t0
-    return {"value": round(w.npts * steps / dt / 1e9, 4), "unit": "Gpts/s", "cores": threads, "kind": "oracle",
-            "sample": "%s: first %d of %d time steps on the full %s grid (FP64, OpenMP over axis 0), "
-                      "%.1f s" % (w.name, steps, w.nt, "x".join(map(str, w.shape)), dt)}
+    out = {"value": round(w.npts * steps / dt / 1e9, 4), "unit": "Gpts/s", "cores": threads, "kind": "oracle",
+           "sample": "%s: first %d of %d time steps on the full %s grid (FP64, OpenMP over axis 0), "
+                     "%.1f s" % (w.name, steps, w.nt, "x".join(map(str, w.shape)), dt),
+           "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count()}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", _ORACLE_ONE_THREAD, ROOT, str(n)], env=env, capture_output=True,
+                           text=True, timeout=300)
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        out["single_thread_value"] = round(one["npts"] / one["s"] / 1e9, 5)
+        out["single_thread_sample"] = "one time step of the same grid on one thread, %.1f s" % one["s"]
+    except Exception as e:   # the single-thread figure is context only
+        out["single_thread_value"] = None
+        out["single_thread_sample"] = "not measured: %s" % type(e).__name__
+    return out
 
 
 def gradient_bench(args, dev, stream):
@@ -412,6 +450,38 @@ def main():
         log("untiled (zchunks %d): %.4f s/step -> %.1f Gpts/s" % (zu, ut, untiled["value"]))
         op.set_schedule(*sched)
 
+    # ---------------------------------------------------------------- plain copy rate on this GPU
+    # zero steps with an initial and a final state: four copies of one time
+    # level through the library's copy kernel (read N floats, write N floats)
+    x = torch.zeros((2,) + tuple(w.shape), dtype=torch.float32, device=dev)
+    op.forward(0, u_init=x, want_final=True)
+    ec = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        op.forward(0, u_init=x, want_final=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ec.append(e0.elapsed_time(e1) * 1e-3)
+    copy_gbs = 4 * 2 * w.npts * 4 / min(ec) / 1e9
+    del x
+    # the sweep's own mix, three streams read and one written (16 B per
+    # point), as a plain elementwise kernel: torch's addcmul over N floats
+    s3 = [torch.empty(w.npts, dtype=torch.float32, device=dev) for _ in range(4)]
+    torch.addcmul(s3[0], s3[1], s3[2], out=s3[3])
+    es = []
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        torch.addcmul(s3[0], s3[1], s3[2], out=s3[3])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        es.append(e0.elapsed_time(e1) * 1e-3)
+    stream_gbs = 16 * w.npts / min(es) / 1e9
+    del s3
+
     # ---------------------------------------------------------------- roofline of the dominant kernel
     # One step = ceil(nt / T) launches of the sweep kernel plus four small
     # kernels (forcing table, two fills, receiver reduction; < 0.1 % of the
@@ -434,7 +504,9 @@ def main():
                 "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": kernel_name(sched, w.so), "algorithmic_bytes_per_launch": alg_bytes,
                 "bytes_per_point_update": bpp, "points_per_launch": w.npts * Tn,
-                "avg_launch_ms": round(t_launch * 1e3, 4), "launches_per_step": launches}
+                "avg_launch_ms": round(t_launch * 1e3, 4), "launches_per_step": launches,
+                "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                "stream_3r1w_GBs": round(stream_gbs, 1), "frac_of_stream_3r1w": round(achieved / stream_gbs, 4)}
 
     # ---------------------------------------------------------------- arithmetic intensity
     # AI of the untiled sweep: useful flops per compulsory byte; the estimators
@@ -443,11 +515,11 @@ def main():
     ai_s = flops_pt / 16.0
     ai = {"flops_per_point_update": flops_pt, "untiled_ai": round(ai_s, 4),
           "naive": round(wave_ai_naive(ai_s, Tn), 4)}
-    if T >= 1:
-        from paper_1806_08299_amd.wave import block_extent
-        ey, ex = block_extent(3, sched[2])
-        for nm, om in (("tight_l2", L2_FLOATS), ("tight_mall", MALL_FLOATS)):
-            ai[nm] = round(wave_ai_tight(ai_s, Tn, w.shape, [w.so // 2] * 3, [w.shape[0], ey, ex], om), 4)
+    from paper_1806_08299_amd.wave import block_extent
+    # tile sizes: the extended tile of the tiled sweep, the 16 x 64 block of the untiled one
+    ey, ex = block_extent(3, sched[2]) if T >= 1 else (16, 64)
+    for nm, om in (("tight_l2", L2_FLOATS), ("tight_mall", MALL_FLOATS)):
+        ai[nm] = round(wave_ai_tight(ai_s, Tn, w.shape, [w.so // 2] * 3, [w.shape[0], ey, ex], om), 4)
     if traffic:
         ai["measured"] = round(flops_pt * w.npts * Tn / traffic, 4)
     ai["compulsory"] = round(flops_pt / bpp, 4)
@@ -463,7 +535,7 @@ def main():
             orders.append(tiling_factor(so, dev, stream, n=128 if args.quick else 512))
             log("order %d: untiled %.1f, tiled %.1f %s -> %.3fx" % (so, orders[-1]["untiled"], orders[-1]["tiled"],
                                                                   orders[-1]["tiled_schedule"], orders[-1]["factor"]))
-    cpu = None if args.no_cpu else cpu_baseline(w)
+    cpu = None if args.no_cpu else cpu_baseline(w, n=args.n)
 
     line = {
         "metric": "Gpts/s fwd & adjoint-grad vs untiled sweep; % HBM roofline (1 MI355X)",
