@@ -184,10 +184,22 @@ __device__ __forceinline__ const SweepArgs& shot_args(const BatchArgs& B, int& b
 // Work item `blk` of a shot: tiles vary fastest, then axis-0 segments, so
 // the workgroups resident at any moment cover one compact front of the grid
 // (neighbouring tiles re-read each other's halo columns from the shared
-// last-level cache while they are still there).
+// last-level cache while they are still there).  Within a segment the tiles
+// are taken in bands of kXcd tile rows, column by column.  Workgroups are
+// dealt to the XCDs round-robin, so work item t + kXcd runs on the XCD of
+// item t and, inside a band, is its neighbour along axis 2: the halo lines
+// the two share come from that XCD's L2.  Rows past the last whole band keep
+// the row-major order.
+constexpr int kXcd = 8;   // XCDs of the chip
 __device__ __forceinline__ void work_item(const SweepArgs& A, int blk, int& tile, int& chunk) {
   chunk = blk / A.ntiles;
   tile = blk % A.ntiles;
+  const int band_tiles = kXcd * A.tiles_x;
+  const int band = tile / band_tiles;
+  if (band < A.ntiles / band_tiles) {
+    const int l = tile - band * band_tiles;
+    tile = (band * kXcd + l % kXcd) * A.tiles_x + l / kXcd;
+  }
 }
 
 // Step of stage k (1-based) of a launch.
