@@ -367,8 +367,13 @@ struct Plan {
   int core_y, core_x;
 };
 
+// Axis-0 segments when the caller gives none.  The untiled 3D sweep runs
+// best with segments of ~20-25 planes on MI355X (592^3: 24-32 segments
+// 298-299 Gpts/s, 12 segments 285), i.e. about 32 workgroups per CU; the
+// time-tiled sweeps want very different counts by depth and order, which
+// wave_autotune finds.
 int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T) {
-  const int64_t target = (kind == KIND_UNTILED) ? 8LL * c->num_cu : 2LL * c->num_cu;
+  const int64_t target = (kind == KIND_UNTILED) ? (c->dim == 3 ? 32LL : 8LL) * c->num_cu : 2LL * c->num_cu;
   int64_t zc = (target + base_blocks - 1) / base_blocks;
   const int64_t min_len = (kind == KIND_UNTILED) ? 16 : std::max<int64_t>(16, 4LL * T * c->R);
   zc = std::min<int64_t>(zc, std::max<int64_t>(1, c->n0 / min_len));
@@ -874,16 +879,16 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
   }
   if (T0 == -2) {
     // Default schedule from measurements on MI355X (592^3, layered model):
-    // depth 2 on 64 x 64 tiles wins at radius 1 in 3D (1.15x); from radius 2
-    // on the halo recomputed by every fused step costs as much or more than
-    // the traffic it saves, so the untiled sweep is the default.
-    // wave_autotune refines by timing on the actual problem.
+    // depth 3 on 32 x 64 tiles wins at radius 1 in 3D (1.36x); from radius 2
+    // on the time-tiled sweep wins only with a tuned segment count (radius
+    // 2) or not at all, so the untiled sweep is the default.  wave_autotune
+    // refines by timing on the actual problem.
     int best = -1;
     if (c->dim == 3 && c->R <= 1) {
       const int oshape = c->shape;
-      if (d->tile_shape == 0) c->shape = 1;
+      if (d->tile_shape == 0) c->shape = 2;
       Plan pl;
-      if (make_plan(c, KIND_TILED, 2, pl) == WAVE_OK) best = 2;
+      if (make_plan(c, KIND_TILED, 3, pl) == WAVE_OK) best = 3;
       else c->shape = oshape;
     }
     c->T = best;
