@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for the time-stepped acoustic-wave sweep.
+"""FP64 CPU oracle for the time-stepped acoustic-wave sweep and for explicit
+diffusion (the paper's Laplace-operator workload).
 
 TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package; the product library never does, and this
@@ -95,8 +96,9 @@ def lib():
         L.og_forward.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int, P, P, P, P, P]
         L.og_adjoint.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
                                  P, P, P, P, ctypes.c_int, P]
+        L.og_diffuse.argtypes = [P, ctypes.c_double, ctypes.c_int, P, P]
         for f in (L.og_fd_coeffs, L.og_laplacian, L.og_sigma, L.og_interp_corners,
-                  L.og_forward, L.og_adjoint):
+                  L.og_forward, L.og_adjoint, L.og_diffuse):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -203,4 +205,15 @@ def adjoint(g: Grid, m, nt: int, resid, hist=None, src_xyz=None, rec_xyz=None,
         out["grad_q"] = gq
     if want_final:
         out["final"] = fin
+    return out
+
+
+def diffuse(g: Grid, a: float, nt: int, u0) -> np.ndarray:
+    """The Laplace-operator family (evaluation chapter), read as explicit
+    diffusion: nt steps of u <- u + dt a (L u) from u0 (g.dt is the step)."""
+    u0 = _f64(u0, g.shape)
+    out = np.empty_like(u0)
+    gc = g.c()
+    if lib().og_diffuse(ctypes.byref(gc), float(a), int(nt), _p(u0), _p(out)) != 0:
+        raise ValueError("og_diffuse failed")
     return out

@@ -41,6 +41,13 @@
  *                 corners of the cell holding xi = x/h, i = floor(xi);
  *                 corners outside the grid are dropped.
  *
+ * The paper's second workload, the Laplace operator family of its evaluation
+ * chapter (first order in time, one time dependency), is never printed
+ * either; it is read as explicit diffusion with a constant diffusivity a:
+ *
+ *   diffusion     u^{n+1} = u^n + dt a (L u^n)
+ *                 with the same Laplacian, ghosts and coefficients as above.
+ *
  * Layout: row-major [n0][n1][n2] (3D) or [n0][n1] (2D); the last axis has unit
  * stride.  Coordinates are in metres from grid node 0 along each axis.
  */
@@ -378,4 +385,28 @@ int og_adjoint(const og_grid *g, const double *m, int nt,
     free(lap);
     free(inj);
     return 0;
+}
+
+/* Explicit diffusion, the paper's Laplace-operator family: nt steps of
+ * u <- u + dt * a * (L u) from u0, result in u_out (both N doubles). */
+int og_diffuse(const og_grid *g, double a, int nt, const double *u0, double *u_out) {
+    if (nt < 0) return -1;
+    long N = og_npts(g);
+    double *u = malloc(N * sizeof(double));
+    double *lap = malloc(N * sizeof(double));
+    if (!u || !lap) {
+        free(u);
+        free(lap);
+        return -2;
+    }
+    memcpy(u, u0, N * sizeof(double));
+    int rc = 0;
+    for (int n = 0; n < nt && rc == 0; ++n) {
+        rc = og_laplacian(g, u, lap);
+        for (long p = 0; p < N; ++p) u[p] = u[p] + g->dt * a * lap[p];
+    }
+    memcpy(u_out, u, N * sizeof(double));
+    free(u);
+    free(lap);
+    return rc;
 }
