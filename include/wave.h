@@ -219,10 +219,55 @@ wave_status wave_tile_extent(int32_t ndim, int32_t tile_shape, int32_t* ey, int3
 /* Flops per point-update of the sweep (adds + multiplies, FMA = 2) for order
  * so in ndim dimensions, and compulsory HBM bytes per point-update of the
  * schedule (T = -1 untiled; damping computed from indices) for mode 0
- * (forward), 1 (forward storing the history, +4 B) or 2 (adjoint reading the
- * history and updating the gradient at every stage, +12 B). Host-only. */
+ * (forward), 1 (forward storing the history, +4 B), 2 (adjoint reading the
+ * history and updating the gradient at every stage, +12 B) or 3 (explicit
+ * diffusion: read one level, write one level per launch, 8/T B). Host-only. */
 double wave_flops_per_point(int32_t ndim, int32_t space_order, int32_t damped);
 double wave_bytes_per_point(int32_t time_tile, int32_t mode);
+
+/* ------------------------------------------------------------------------
+ * Explicit diffusion: the Laplace-operator workload of the paper's evaluation
+ * chapter (first order in time, one time dependency).  The paper never prints
+ * its equation; it is read as
+ *     u^{n+1} = u^n + dt a (L u^n)
+ * with the Laplacian, coefficients and zero ghosts of the wave sweep above
+ * and a constant diffusivity a.  It runs on the same schedules (untiled
+ * sweep or time-tiled with depth, skew, tile shape and axis-0 segments) and
+ * kernels; the per-point update is u + lap with the weights scaled by
+ * dt a / h_axis^2 (FP64 on the host, rounded once).  Every schedule gives the
+ * same bits.  Layout as above (axis 0 streamed, last axis unit stride). */
+typedef struct diff_desc {
+  int32_t ndim;          /* 2 or 3 */
+  int32_t space_order;   /* even, 2..16 */
+  int64_t shape[3];      /* grid, n0 n1 [n2] */
+  double spacing[3];     /* per axis */
+  double dt;             /* time step */
+  double alpha;          /* diffusivity a (> 0); units spacing^2 / time */
+  int32_t time_tile;     /* -1 or 0: untiled sweep; T >= 1: fused steps per launch */
+  int32_t skew;          /* 0 = r; must be >= r */
+  int32_t tile_shape;    /* as in wave_desc */
+  int32_t zchunks;       /* as in wave_desc */
+} diff_desc;
+
+/* Flops per point-update of explicit diffusion (FMA = 2). Host-only. */
+double diff_flops_per_point(int32_t ndim, int32_t space_order);
+
+/* Bytes of device state for `d`: two levels of N floats (0 if d is invalid). */
+size_t diff_state_bytes(const diff_desc* d);
+
+/* Validate `d` (as wave_desc, plus alpha > 0 finite) and the stability limit
+ * dt a sum_a rho / h_a^2 <= 2 (rho as for wave_init), and carve the state.
+ * The context takes wave_set_schedule, wave_get_schedule, wave_last_error
+ * and wave_destroy; the wave-equation calls reject it with WAVE_ESTATE.
+ * Errors: WAVE_EINVAL, WAVE_ESKEW, WAVE_ECFL, WAVE_ENOMEM, WAVE_EUNSUPPORTED. */
+wave_status diff_init(const diff_desc* d, void* state_dev, size_t state_bytes, void* hip_stream,
+                      wave_ctx** out);
+
+/* nt steps from u0_dev [N] (device, read only) into u_out_dev [N] (device);
+ * the two must not overlap.  Intermediate levels live in the state.  nt == 0
+ * copies.  Asynchronous on the context's stream.  Errors: WAVE_EINVAL,
+ * WAVE_ESTATE (not a diffusion context), WAVE_EUNSUPPORTED, WAVE_EHIP. */
+wave_status diff_forward(wave_ctx* ctx, int32_t nt, const float* u0_dev, float* u_out_dev);
 
 const char* wave_strerror(wave_status s);
 const char* wave_last_error(const wave_ctx* ctx);

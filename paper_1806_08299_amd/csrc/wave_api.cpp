@@ -45,6 +45,7 @@ struct BatchGraph {
 
 struct wave_ctx {
   wave_desc d;
+  int eq = 0;                    // 0: wave equation (wave_init); 1: explicit diffusion (diff_init)
   int R = 0;
   int dim = 3;
   int64_t n0 = 1, n1 = 1, n2 = 1, N = 0;
@@ -446,7 +447,8 @@ wave_status launch_window(wave_ctx* c, const Plan& p, SweepArgs A) {
   A.zchunk = p.zchunk;
   dim3 grid((unsigned)A.nblocks);
   int mode = MODE_FWD;
-  if (A.grad) mode = MODE_ADJ;
+  if (c->eq == 1) mode = MODE_DIFF;
+  else if (A.grad) mode = MODE_ADJ;
   else if (A.hist) mode = MODE_HIST;
   if (c->rec) {
     RecOp op;
@@ -683,12 +685,13 @@ int tiled_tmax(int R, int dim, int shape) {
 
 hipError_t launch_sweep(int R, int kind, int T, int dim, int mode, int shape, const SweepArgs& A, dim3 grid,
                         size_t lds, hipStream_t s) {
-  if (mode < 0 || mode > 2) return hipErrorInvalidValue;
+  if (mode < 0 || mode > 3) return hipErrorInvalidValue;
 #define WAVE_CASE(RR)                                                                  \
   case RR:                                                                             \
     return mode == 0 ? launch_sweep_r##RR##_m0(kind, T, dim, shape, A, grid, lds, s)  \
          : mode == 1 ? launch_sweep_r##RR##_m1(kind, T, dim, shape, A, grid, lds, s)  \
-                     : launch_sweep_r##RR##_m2(kind, T, dim, shape, A, grid, lds, s);
+         : mode == 2 ? launch_sweep_r##RR##_m2(kind, T, dim, shape, A, grid, lds, s)  \
+                     : launch_sweep_r##RR##_m3(kind, T, dim, shape, A, grid, lds, s);
   switch (R) {
     WAVE_CASE(1) WAVE_CASE(2) WAVE_CASE(3) WAVE_CASE(4) WAVE_CASE(5) WAVE_CASE(6) WAVE_CASE(7) WAVE_CASE(8)
     default: return hipErrorInvalidValue;
@@ -795,6 +798,7 @@ __global__ void k_min_reduce(const float* m, int64_t n, float* out) {
 
 wave_status wave_set_model(wave_ctx* c, const float* m) {
   if (!c || !m) return fail(c, WAVE_EINVAL, "null model");
+  if (c->eq != 0) return fail(c, WAVE_ESTATE, "not a wave-equation context");
   // min(m) via the wavefield buffer w[3] as temporary space (overwritten by any sweep anyway)
   const int nb = 1024;
   hipLaunchKernelGGL(k_min_reduce, dim3(nb), dim3(256), 0, c->stream, m, c->N, c->w[3]);
@@ -919,6 +923,7 @@ wave_status wave_forward(wave_ctx* c, int32_t nt, int32_t nsrc, const double* sr
                          void* scratch, size_t scratch_bytes) {
   if (!c) return WAVE_EINVAL;
   c->err.clear();
+  if (c->eq != 0) return fail(c, WAVE_ESTATE, "not a wave-equation context (diffusion contexts use diff_forward)");
   c->ck.valid = false;
   if (nt < 0 || K < 0) return fail(c, WAVE_EINVAL, "negative nt or checkpoint interval");
   wave_status s;
@@ -1035,6 +1040,7 @@ wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const doubl
                               int32_t K, int32_t reuse, void* scratch, size_t scratch_bytes) {
   if (!c) return WAVE_EINVAL;
   c->err.clear();
+  if (c->eq != 0) return fail(c, WAVE_ESTATE, "not a wave-equation context");
   if (nt < 0 || K < 1) return fail(c, WAVE_EINVAL, "need nt >= 0 and a checkpoint interval >= 1");
   if (!grad_m) return fail(c, WAVE_EINVAL, "null grad_m");
   if (nt > 0 && nrec > 0 && !resid) return fail(c, WAVE_EINVAL, "null residual");
@@ -1124,6 +1130,8 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const 
   if (!ctxs || nshots < 1 || !ctxs[0]) return WAVE_EINVAL;
   wave_ctx* lead = ctxs[0];
   lead->err.clear();
+  for (int i = 0; i < nshots; ++i)
+    if (ctxs[i] && ctxs[i]->eq != 0) return fail(lead, WAVE_ESTATE, "a shot context is not a wave-equation context");
   if (nt < 0) return fail(lead, WAVE_EINVAL, "negative nt");
   if (!nsrc || !src_xyz || !wavelet_dev || !nrec || !rec_xyz || !rec_dev || !scratch_dev || !scratch_bytes)
     return fail(lead, WAVE_EINVAL, "null per-shot array");
@@ -1245,6 +1253,7 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const 
 wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, void* scratch,
                           size_t scratch_bytes, double* best) {
   if (!c || trial_steps < 1 || repeats < 1) return WAVE_EINVAL;
+  if (c->eq != 0) return fail(c, WAVE_ESTATE, "not a wave-equation context");
   const Layout L = layout(c, trial_steps, 0, 0, 0, 0);
   if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
   c->gen++;
@@ -1373,10 +1382,153 @@ double wave_bytes_per_point(int32_t T, int32_t mode) {
   // history +4 B (write or read); imaging gradient +8 B (read-modify-write
   // at every stage of the window).
   const double Tt = T < 1 ? 1.0 : (double)T;
+  if (mode == 3) return 8.0 / Tt;   // diffusion: read u^n, write u^{n+T}
   double base = (T <= 1) ? 16.0 : 20.0 / Tt;
   if (mode == 1) base += 4.0;
   if (mode == 2) base += 4.0 + 8.0;
   return base;
+}
+
+double diff_flops_per_point(int32_t ndim, int32_t so) {
+  // centre product, per axis per pair one add + one FMA, the final add
+  const double r = so / 2;
+  return 2.0 + 3.0 * ndim * r;
+}
+
+// ====================================================== explicit diffusion
+
+// The Laplace-operator workload of the paper's evaluation chapter, read as
+// explicit diffusion u^{n+1} = u^n + dt a (L u^n) with zero ghosts.  It runs
+// on the wave context's schedule, plans and sweep kernels in MODE_DIFF.
+
+static wave_desc diff_as_wave(const diff_desc* d) {
+  wave_desc w{};
+  w.ndim = d->ndim;
+  w.space_order = d->space_order;
+  for (int a = 0; a < 3; ++a) {
+    w.shape[a] = d->shape[a];
+    w.spacing[a] = d->spacing[a];
+  }
+  w.dt = d->dt;
+  w.nbl = 0;
+  w.sigma_max = 0.0;
+  w.time_tile = d->time_tile;
+  w.skew = d->skew;
+  w.tile_shape = d->tile_shape;
+  w.zchunks = d->zchunks;
+  return w;
+}
+
+// Von Neumann limit of explicit diffusion: dt a sum_a rho / h_a^2 <= 2, with
+// rho the magnitude of the weights' symbol at the Nyquist wavenumber.
+static double diff_stability(const diff_desc* d) {
+  double c[9];
+  fd_weights(d->space_order, c);
+  double rho = -c[0];
+  for (int j = 1; j <= d->space_order / 2; ++j) rho -= 2.0 * c[j] * ((j & 1) ? -1.0 : 1.0);
+  double s = 0.0;
+  for (int a = 0; a < d->ndim; ++a) s += rho / (d->spacing[a] * d->spacing[a]);
+  return d->dt * d->alpha * s / 2.0;
+}
+
+size_t diff_state_bytes(const diff_desc* d) {
+  if (!d) return 0;
+  const wave_desc w = diff_as_wave(d);
+  std::string msg;
+  wave_status s = check_desc(&w, msg);
+  if (s != WAVE_OK && s != WAVE_ESKEW) return 0;
+  return 2 * align_up(sizeof(float) * npts_of(&w));
+}
+
+wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void* stream, wave_ctx** out) {
+  if (!out) return WAVE_EINVAL;
+  *out = nullptr;
+  if (!d) return WAVE_EINVAL;
+  const wave_desc w = diff_as_wave(d);
+  std::string msg;
+  wave_status s = check_desc(&w, msg);
+  if (s != WAVE_OK) return s;
+  if (!(d->alpha > 0.0) || !std::isfinite(d->alpha)) return WAVE_EINVAL;
+  if (diff_stability(d) > 1.0 + 1e-12) return WAVE_ECFL;
+  if (!state) return WAVE_EINVAL;
+  if (state_bytes < diff_state_bytes(d)) return WAVE_ENOMEM;
+  static std::atomic<uint64_t> next_id{1u << 30};
+  wave_ctx* c = new wave_ctx();
+  c->id = ++next_id;
+  c->eq = 1;
+  c->d = w;
+  c->R = d->space_order / 2;
+  c->dim = d->ndim;
+  c->n0 = d->shape[0];
+  c->n1 = d->ndim == 3 ? d->shape[1] : 1;
+  c->n2 = d->ndim == 3 ? d->shape[2] : d->shape[1];
+  c->N = npts_of(&w);
+  c->stream = (hipStream_t)stream;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+      c->max_lds = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
+    }
+  }
+  // weights times dt a / h_axis^2, FP64 then rounded once
+  double cw[9];
+  fd_weights(d->space_order, cw);
+  double k[3] = {0, 0, 0};
+  for (int a = 0; a < d->ndim; ++a) k[a] = d->dt * d->alpha / (d->spacing[a] * d->spacing[a]);
+  const double kz = k[0], ky = d->ndim == 3 ? k[1] : 0.0, kx = k[d->ndim - 1];
+  c->C.c0 = (float)(cw[0] * (kz + ky + kx));
+  for (int j = 1; j <= c->R; ++j) {
+    c->C.w[0][j - 1] = (float)(cw[j] * kz);
+    c->C.w[1][j - 1] = (float)(cw[j] * ky);
+    c->C.w[2][j - 1] = (float)(cw[j] * kx);
+  }
+  char* p = (char*)state;
+  c->w[0] = (float*)p;
+  c->w[1] = (float*)(p + align_up(sizeof(float) * c->N));
+  // time_tile 0: the untiled sweep (wave_set_schedule picks others)
+  s = apply_schedule(c, d->time_tile == 0 ? -1 : d->time_tile, d->skew, d->tile_shape, d->zchunks);
+  if (s != WAVE_OK) {
+    delete c;
+    return s;
+  }
+  c->err.clear();
+  *out = c;
+  return WAVE_OK;
+}
+
+wave_status diff_forward(wave_ctx* c, int32_t nt, const float* u0, float* u_out) {
+  if (!c) return WAVE_EINVAL;
+  c->err.clear();
+  if (c->eq != 1) return fail(c, WAVE_ESTATE, "not a diffusion context");
+  if (nt < 0) return fail(c, WAVE_EINVAL, "negative nt");
+  if (!u0 || !u_out) return fail(c, WAVE_EINVAL, "null field");
+  if (u0 == u_out) return fail(c, WAVE_EINVAL, "u_out must not alias u0");
+  if (nt == 0) return copy(c, u0, u_out, c->N);
+  const bool untiled = c->T < 0;
+  const float* src = u0;
+  int k = 0, done = 0;
+  while (done < nt) {
+    const int T = untiled ? 1 : std::min(c->T, nt - done);
+    Plan p;
+    wave_status s = make_plan(c, untiled ? KIND_UNTILED : KIND_TILED, T, p);
+    if (s != WAVE_OK) return s;
+    SweepArgs A = base_args(c);
+    A.cur = src;
+    A.prev = src;   // not read in this mode
+    A.b = src;      // not read in this mode
+    float* dst = (done + T == nt) ? u_out : c->w[k];
+    A.outA = dst;
+    A.outB = nullptr;
+    A.step0 = done;
+    A.dir = 1;
+    if ((s = launch_window(c, p, A))) return s;
+    src = dst;
+    k ^= 1;
+    done += T;
+  }
+  return WAVE_OK;
 }
 
 }  // extern "C"

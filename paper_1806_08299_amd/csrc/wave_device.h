@@ -60,6 +60,27 @@ __device__ __forceinline__ float wave_num(const Coefs& C, float uc,
   return __builtin_fmaf(b, t, a);
 }
 
+// One grid point of explicit diffusion (the Laplace-operator workload):
+// u + (C.c0 u + sum of weighted pairs), the weights already scaled by
+// dt a / h_axis^2.  Same operation order as wave_num's Laplacian (centre,
+// then axis z, y, x pairs), then one addition.
+template <int R, bool HAS_Y>
+__device__ __forceinline__ float diff_next(const Coefs& C, float uc,
+                                           const float* zm, const float* zp,
+                                           const float* ym, const float* yp,
+                                           const float* xm, const float* xp) {
+  float lap = C.c0 * uc;
+#pragma unroll
+  for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[0][j], zm[j] + zp[j], lap);
+  if (HAS_Y) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[1][j], ym[j] + yp[j], lap);
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[2][j], xm[j] + xp[j], lap);
+  return uc + lap;
+}
+
 // Inside the absorbing layer divide by (1 + st) through the hardware
 // reciprocal; elsewhere (st == 0) the numerator is the result.
 __device__ __forceinline__ float wave_damp(float num, float st) {
@@ -97,8 +118,9 @@ struct SweepAux {
   float* smp_out;              // [steps][smp.npts]
 };
 
-// Kernel modes.
-enum : int { MODE_FWD = 0, MODE_HIST = 1, MODE_ADJ = 2 };
+// Kernel modes: the wave sweep forward, forward storing the history, adjoint
+// with imaging; explicit diffusion (one input level, no b, no damping).
+enum : int { MODE_FWD = 0, MODE_HIST = 1, MODE_ADJ = 2, MODE_DIFF = 3 };
 
 // Everything a sweep launch needs (passed by value).
 struct SweepArgs {

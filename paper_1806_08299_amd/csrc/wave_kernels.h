@@ -1,5 +1,5 @@
 // wave_kernels.h -- sweep kernels (templates), instantiated per stencil radius
-// in wave_r<R>.hip.
+// and mode in wave_r<R>_m<M>.hip (batched variants: wave_r<R>_b<M>.hip).
 //
 // Layout: one FP32 array per time level, row-major [n0][n1][n2] (2D: n1 == 1),
 // axis 2 unit stride (the 64 lanes of a wavefront walk it, so every global
@@ -23,6 +23,12 @@
 //               other.  Stage k is valid on the tile shrunk by k*skew per side;
 //               after T stages the core is exact.  Each stage's input plane is
 //               staged in LDS; the z windows of every level live in registers.
+//
+// Modes.  MODE_FWD / MODE_HIST / MODE_ADJ sweep the wave equation (forward,
+// forward storing every level, adjoint with the imaging condition fused).
+// MODE_DIFF sweeps explicit diffusion, the paper's Laplace-operator workload:
+// the same streaming and tiling with one input level -- no u^{n-1} or b
+// stream, no damping or point terms -- writing to a different array.
 //
 // Register windows.  The (2R+1)-plane window of every level is a ring in
 // registers.  In the tiled sweep the z loop is unrolled by the window length
@@ -226,6 +232,7 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
   int blk;
   const SweepArgs& A = shot_args(P, blk);
   constexpr bool HY = (DIM == 3);
+  constexpr bool DF = (MODE == MODE_DIFF);   // diffusion: one input level, no b
   constexpr int W = 2 * R + 1;
   constexpr bool ROT = W <= kMaxUnrollWUntiled;
   constexpr int TY = HY ? NW * RY : 1;
@@ -313,8 +320,8 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
     for (int i = 0; i < RY; ++i) {
       zw[i][0] = 0.0f;
       pc[i] = bload(rc, col[i], sc);
-      pp[i] = bload(rp, col[i], s1);
-      pb[i] = bload(rb, col[i], s1);
+      pp[i] = DF ? 0.0f : bload(rp, col[i], s1);
+      pb[i] = DF ? 0.0f : bload(rb, col[i], s1);
     }
 #pragma unroll
     for (int h = 0; h < HPT; ++h) ph[h] = bload(rc, hcol[h], s1);
@@ -323,7 +330,8 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
   const int step = A.step0;
   const int64_t N = (int64_t)n0 * A.s0;
   // history / gradient: one time level per launch
-  const rsrc_t rh = (MODE != MODE_FWD) ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ro;
+  constexpr bool HIST = (MODE == MODE_HIST || MODE == MODE_ADJ);
+  const rsrc_t rh = HIST ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ro;
   const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ro;
   const int nit = zb - za;
   // One plane; `rot` is the rotation after this iteration's push.
@@ -344,8 +352,10 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
         pc[i] = bload(rc, col[i], sc);
-        pp[i] = bload(rp, col[i], s1);
-        pb[i] = bload(rb, col[i], s1);
+        if constexpr (!DF) {
+          pp[i] = bload(rp, col[i], s1);
+          pb[i] = bload(rb, col[i], s1);
+        }
       }
 #pragma unroll
       for (int h = 0; h < HPT; ++h) ph[h] = bload(rc, hcol[h], s1);
@@ -402,9 +412,13 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
           const float sty = HY ? damp_term(gy0 + wv * RY + i, A.n1, A.nbl, A.st_coef) : 0.0f;
           st[i] = (stz + sty) + stx[HY ? 0 : i];
         }
-        v[i] = wave_num<R, HY>(A.C, zw[i][(R + rot) % W], zm, zp, ym, yp, xm, xp, up[i], bb[i], st[i], f, DM,
-                               EV && fz);
-        if (DM) v[i] = wave_damp(v[i], st[i]);
+        if constexpr (DF) {
+          v[i] = diff_next<R, HY>(A.C, zw[i][(R + rot) % W], zm, zp, ym, yp, xm, xp);
+        } else {
+          v[i] = wave_num<R, HY>(A.C, zw[i][(R + rot) % W], zm, zp, ym, yp, xm, xp, up[i], bb[i], st[i], f, DM,
+                                 EV && fz);
+          if (DM) v[i] = wave_damp(v[i], st[i]);
+        }
       }
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
@@ -421,7 +435,9 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
     };
     using TT = std::true_type;
     using FF = std::false_type;
-    if (fz || sz) {
+    if constexpr (DF) {
+      rows(FF{}, FF{});
+    } else if (fz || sz) {
       if (dmp) rows(TT{}, TT{}); else rows(FF{}, TT{});
     } else {
       if (dmp) rows(TT{}, FF{}); else rows(FF{}, FF{});
@@ -454,6 +470,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
   int blk;
   const SweepArgs& A = shot_args(P, blk);
   constexpr bool HY = (DIM == 3);
+  constexpr bool DF = (MODE == MODE_DIFF);   // diffusion: one input level, no b
   constexpr int W = 2 * R + 1;
   constexpr bool ROT = W <= kMaxUnrollW;
   constexpr int EY = HY ? NW * RY : 1;
@@ -526,13 +543,13 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       pc[i] = bload(rc, col[i], sc);
-      pp[i] = bload(rp, col[i], sp);
+      pp[i] = DF ? 0.0f : bload(rp, col[i], sp);
     }
 #pragma unroll
     for (int k = 0; k < T; ++k) {
       const uint32_t sb = sg.off(zs - (k + 1) * R);
 #pragma unroll
-      for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i], sb);
+      for (int i = 0; i < RY; ++i) pb[k][i] = DF ? 0.0f : bload(rb, col[i], sb);
     }
   }
   __syncthreads();
@@ -556,13 +573,15 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
         pc[i] = bload(rc, col[i], sc);
-        pp[i] = bload(rp, col[i], sp);
+        if constexpr (!DF) pp[i] = bload(rp, col[i], sp);
       }
+      if constexpr (!DF) {
 #pragma unroll
-      for (int k = 0; k < T; ++k) {
-        const uint32_t sb = sg.off(zn - (k + 1) * R);
+        for (int k = 0; k < T; ++k) {
+          const uint32_t sb = sg.off(zn - (k + 1) * R);
 #pragma unroll
-        for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i], sb);
+          for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i], sb);
+        }
       }
     }
     // Stage the input plane of every stage in LDS: for stage k+1 that is level
@@ -612,7 +631,8 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
         const bool fz = EV && zk >= A.inj_zlo && zk < A.inj_zhi;
         const bool sz = EV && zown && zk >= A.smp_zlo && zk < A.smp_zhi;
         const uint32_t so = sg.off(zk, za, zb);   // stores: owned planes only
-        const rsrc_t rh = (MODE != MODE_FWD) ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
+        constexpr bool HIST = (MODE == MODE_HIST || MODE == MODE_ADJ);
+        const rsrc_t rh = HIST ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
         const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ra;
         float v[RY], st[RY], upv[RY], fr[RY];
         const int ybase = gy0 + (HY ? wrow0 : 0), xbase = gx0 + (HY ? 0 : wv * RY * 64);
@@ -639,9 +659,17 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
             const float sty = HY ? damp_term(gy0 + wrow0 + i, A.n1, A.nbl, A.st_coef) : 0.0f;
             st[i] = (stz + sty) + stx[HY ? 0 : i];
           }
-          v[i] = wave_num<R, HY>(A.C, win[k - 1][i][(R + rot) % W], zm, zp, ym, yp, xm, xp, upv[i],
-                                 bin[k - 1][i], st[i], f, DM, EV && fz);
-          if (DM) v[i] = wave_damp(v[i], st[i]);
+          if constexpr (DF) {
+            // Outside the grid the wave update is exactly 0 (b reads 0 there);
+            // diffusion's u + lap is not, so zero it: the next stage must see
+            // the zero ghosts the untiled sweep reads.
+            const float d = diff_next<R, HY>(A.C, win[k - 1][i][(R + rot) % W], zm, zp, ym, yp, xm, xp);
+            v[i] = (col[i] != kOOB && zk >= 0 && zk < n0) ? d : 0.0f;
+          } else {
+            v[i] = wave_num<R, HY>(A.C, win[k - 1][i][(R + rot) % W], zm, zp, ym, yp, xm, xp, upv[i],
+                                   bin[k - 1][i], st[i], f, DM, EV && fz);
+            if (DM) v[i] = wave_damp(v[i], st[i]);
+          }
         }
         // in range only for core points of owned planes
         auto outoff = [&](int i) {
@@ -660,7 +688,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
           }
           if (k == T) {
             bstore(ra, o, so, v[i]);
-            bstore(rB, o, so, win[k - 1][i][(R + rot) % W]);
+            if constexpr (!DF) bstore(rB, o, so, win[k - 1][i][(R + rot) % W]);
           }
         }
         if (EV && sz) sample_rows<RY, HY>(A, zk, ybase, xbase, lane, step, v, [&](int i) { return outoff(i) != kOOB; });
@@ -672,7 +700,9 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
     };
     using TT = std::true_type;
     using FF = std::false_type;
-    if (any_ev) {
+    if constexpr (DF) {
+      stages(FF{}, FF{});
+    } else if (any_ev) {
       if (any_dmp) stages(TT{}, TT{}); else stages(FF{}, TT{});
     } else {
       if (any_dmp) stages(TT{}, FF{}); else stages(FF{}, FF{});

@@ -61,6 +61,33 @@ def make_desc(shape, spacing, dt, space_order, nbl=0, sigma_max=0.0, time_tile=-
     return d
 
 
+class diff_desc(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("space_order", ctypes.c_int32),
+                ("shape", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3),
+                ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("time_tile", ctypes.c_int32), ("skew", ctypes.c_int32),
+                ("tile_shape", ctypes.c_int32), ("zchunks", ctypes.c_int32)]
+
+
+def make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile=-1, skew=0, tile_shape=0,
+                   zchunks=0) -> diff_desc:
+    d = diff_desc()
+    shape = tuple(int(s) for s in shape)
+    d.ndim = len(shape)
+    d.space_order = int(space_order)
+    sp = tuple(float(h) for h in (spacing if np.ndim(spacing) else (spacing,) * len(shape)))
+    for a in range(3):
+        d.shape[a] = shape[a] if a < len(shape) else 1
+        d.spacing[a] = sp[a] if a < len(shape) else 1.0
+    d.dt = float(dt)
+    d.alpha = float(alpha)
+    d.time_tile = int(time_tile)
+    d.skew = int(skew)
+    d.tile_shape = int(tile_shape)
+    d.zchunks = int(zchunks)
+    return d
+
+
 _lib = None
 P = ctypes.c_void_p
 
@@ -91,6 +118,10 @@ def lib():
             "wave_ai_tight": (dbl, [dbl, i32, i32, P, P, P, dbl]),
             "wave_flops_per_point": (dbl, [i32, i32, i32]),
             "wave_bytes_per_point": (dbl, [i32, i32]),
+            "diff_flops_per_point": (dbl, [i32, i32]),
+            "diff_state_bytes": (sz, [P]),
+            "diff_init": (i32, [P, P, sz, P, ctypes.POINTER(P)]),
+            "diff_forward": (i32, [P, i32, P, P]),
             "wave_strerror": (ctypes.c_char_p, [i32]),
             "wave_last_error": (ctypes.c_char_p, [P]),
             "wave_destroy": (None, [P]),
@@ -292,6 +323,26 @@ def wave_destroy(ctx):
         lib().wave_destroy(ctx)
 
 
+def diff_flops_per_point(ndim, space_order) -> float:
+    return float(lib().diff_flops_per_point(ndim, space_order))
+
+
+def diff_state_bytes(desc: diff_desc) -> int:
+    return int(lib().diff_state_bytes(ctypes.byref(desc)))
+
+
+def diff_init(desc: diff_desc, state: torch.Tensor, stream=None):
+    out = ctypes.c_void_p()
+    st = lib().diff_init(ctypes.byref(desc), ctypes.c_void_p(state.data_ptr()),
+                         state.numel() * state.element_size(), _stream(stream), ctypes.byref(out))
+    _check(st)
+    return out
+
+
+def diff_forward(ctx, nt: int, u0: torch.Tensor, u_out: torch.Tensor):
+    _check(lib().diff_forward(ctx, int(nt), _dptr(u0), _dptr(u_out)), ctx)
+
+
 # ------------------------------------------------------------------ convenience
 
 class WaveOp:
@@ -411,3 +462,45 @@ class WaveFn(torch.autograd.Function):
                                  want_grad_wavelet=ctx.needs_input_grad[1], reuse=reuse)
         op._fwd_token = None               # adjoint_grad overwrote the scratch
         return gm, gq, None, None, None, None
+
+
+class DiffOp:
+    """Explicit diffusion u <- u + dt a (L u) (the Laplace-operator workload)
+    on the sweep engine: a diffusion context plus its two-level state."""
+
+    def __init__(self, shape, spacing, dt, alpha, space_order, time_tile=-1, skew=0, tile_shape=0, zchunks=0,
+                 device="cuda"):
+        self.desc = make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile, skew, tile_shape, zchunks)
+        self.shape = tuple(int(s) for s in shape)
+        self.ndim = len(self.shape)
+        self.device = torch.device(device)
+        nbytes = diff_state_bytes(self.desc)
+        if nbytes == 0:
+            raise WaveError(-1, "invalid descriptor")
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ctx = diff_init(self.desc, self.state)
+
+    def __del__(self):
+        try:
+            wave_destroy(self.ctx)
+        except Exception:
+            pass
+
+    @property
+    def npts(self):
+        return int(np.prod(self.shape))
+
+    def set_schedule(self, time_tile, skew=0, tile_shape=0, zchunks=0):
+        wave_set_schedule(self.ctx, time_tile, skew, tile_shape, zchunks)
+
+    def schedule(self):
+        return wave_get_schedule(self.ctx)
+
+    def forward(self, nt: int, u0: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        u0 = u0.to(self.device, torch.float32).contiguous()
+        if tuple(u0.shape) != self.shape:
+            raise ValueError("u0 must have the grid's shape")
+        if out is None:
+            out = torch.empty_like(u0)
+        diff_forward(self.ctx, nt, u0, out)
+        return out

@@ -32,7 +32,7 @@ def W():
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"\b(wave_[a-z_]+)\s*\(", src)
+    names = re.findall(r"\b((?:wave|diff)_[a-z_]+)\s*\(", src)
     return sorted(set(names))
 
 
@@ -40,7 +40,7 @@ def test_header_symbols_exported(W):
     names = declared_functions()
     assert len(names) >= 15
     out = subprocess.run(["nm", "-D", "--defined-only", W.LIB_PATH], capture_output=True, text=True).stdout
-    exported = set(re.findall(r"\bT (wave_[a-z_]+)$", out, flags=re.M))
+    exported = set(re.findall(r"\bT ((?:wave|diff)_[a-z_]+)$", out, flags=re.M))
     missing = [n for n in names if n not in exported]
     assert not missing, missing
     for n in names:
@@ -68,6 +68,21 @@ def test_flop_and_byte_counts(W):
     assert W.wave_bytes_per_point(1, 0) == 16.0
     assert W.wave_bytes_per_point(4, 0) == 5.0
     assert W.wave_bytes_per_point(2, 1) == 14.0
+    # explicit diffusion: centre, per axis and radius one add + one FMA, the final add;
+    # one level read and one written per launch
+    assert W.diff_flops_per_point(3, 8) == 2 + 3 * 3 * 4
+    assert W.wave_bytes_per_point(-1, 3) == 8.0
+    assert W.wave_bytes_per_point(4, 3) == 2.0
+
+
+def test_diff_state_bytes_and_validation(W):
+    d = W.make_diff_desc((48, 40, 72), 0.1, 1e-4, 0.5, 8)
+    assert W.diff_state_bytes(d) >= 2 * 4 * 48 * 40 * 72
+    for bad in (dict(space_order=7), dict(ndim=1), dict(dt=-1.0)):
+        dd = W.make_diff_desc((48, 40, 72), 0.1, 1e-4, 0.5, 8)
+        for k, v in bad.items():
+            setattr(dd, k, v)
+        assert W.diff_state_bytes(dd) == 0
 
 
 def _table():

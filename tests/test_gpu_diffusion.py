@@ -1,0 +1,110 @@
+"""Explicit diffusion (the paper's Laplace-operator workload) on the sweep
+engine, through the C ABI (diff_init / diff_forward):
+
+* against the FP64 oracle (oracle.diffuse) within relative L2 1e-5, at every
+  space order 2..16, 3D and 2D, on grids spanning several tiles with ragged
+  edges;
+* every time-tiled schedule (depth, tile shape, axis-0 segments, a last
+  window shorter than the depth) bitwise equal to the untiled sweep;
+* edge cases: zero steps, grids thinner than the stencil, aliasing and
+  wrong-context errors, the stability check.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import waveinputs as wi
+
+pytestmark = pytest.mark.gpu
+
+
+def _op(w, **kw):
+    from paper_1806_08299_amd import DiffOp
+    return DiffOp(w.shape, w.spacing, w.dt, w.alpha, w.so, **kw)
+
+
+def _oracle(w, nt, u0=None):
+    g = oracle.Grid(w.shape, w.spacing, w.dt, w.so)
+    return oracle.diffuse(g, w.alpha, nt, (w.u0 if u0 is None else u0).astype(np.float64))
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 16])
+def test_diffusion_against_oracle_3d(so):
+    w = wi.laplace(shape=(37, 70, 150), so=so, nt=24, seed=so)
+    print("diffusion 3D so%d" % so, flush=True)
+    op = _op(w)
+    got = op.forward(w.nt, torch.from_numpy(w.u0).cuda()).cpu().numpy().astype(np.float64)
+    ref = _oracle(w, w.nt)
+    assert rel(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("so", [4, 16])
+def test_diffusion_against_oracle_2d(so):
+    w = wi.laplace(shape=(90, 1100), so=so, nt=30, seed=20 + so)
+    print("diffusion 2D so%d" % so, flush=True)
+    op = _op(w)
+    got = op.forward(w.nt, torch.from_numpy(w.u0).cuda()).cpu().numpy().astype(np.float64)
+    assert rel(got, _oracle(w, w.nt)) <= 1e-5
+
+
+def _schedules(so, ndim):
+    from paper_1806_08299_amd.wave import wave_tiled_max_depth
+    out = []
+    for shape in ((1, 2) if ndim == 3 else (0,)):
+        for T in range(1, wave_tiled_max_depth(so, ndim, shape or 1) + 1):
+            for zc in (0, 3):
+                out.append((T, shape, zc))
+    return out
+
+
+@pytest.mark.parametrize("so,shape", [(2, (45, 70, 150)), (4, (45, 70, 150)), (8, (45, 70, 150)),
+                                      (16, (60, 50, 140)), (4, (70, 1200)), (8, (70, 1200))])
+def test_diffusion_schedules_bitwise(so, shape):
+    w = wi.laplace(shape=shape, so=so, nt=11, seed=3)
+    op = _op(w)
+    u0 = torch.from_numpy(w.u0).cuda()
+    base = op.forward(w.nt, u0)
+    for zc in (0, 5):
+        op.set_schedule(-1, 0, 0, zc)
+        assert torch.equal(op.forward(w.nt, u0), base), ("untiled", zc)
+    for T, tshape, zc in _schedules(so, len(shape)):
+        print("diffusion so%d %s T=%d shape=%d zc=%d" % (so, shape, T, tshape, zc), flush=True)
+        op.set_schedule(T, 0, tshape, zc)
+        assert torch.equal(op.forward(w.nt, u0), base), (T, tshape, zc)
+    if len(shape) == 3 and so <= 8:   # a wider skew than the radius
+        op.set_schedule(2, so // 2 + 1, 1, 0)
+        assert torch.equal(op.forward(w.nt, u0), base)
+
+
+def test_diffusion_edge_cases():
+    from paper_1806_08299_amd import DiffOp
+    from paper_1806_08299_amd.wave import WaveError, wave_forward
+    w = wi.laplace(shape=(20, 30, 70), so=8, nt=5, seed=9)
+    op = _op(w)
+    u0 = torch.from_numpy(w.u0).cuda()
+    assert torch.equal(op.forward(0, u0), u0)                          # zero steps copy
+    with pytest.raises(WaveError) as e:
+        from paper_1806_08299_amd.wave import diff_forward
+        diff_forward(op.ctx, 3, u0, u0)                                   # output aliases input
+    assert e.value.status == -1
+    with pytest.raises(WaveError) as e:
+        wave_forward(op.ctx, 1, None, None, None, None, None, None, 0, torch.empty(256, dtype=torch.uint8,
+                                                                                  device="cuda"), 3)
+    assert e.value.status == -6                                          # not a wave-equation context
+    with pytest.raises(WaveError) as e:
+        DiffOp(w.shape, w.spacing, 10 * w.dt, w.alpha, w.so)            # beyond the stability limit
+    assert e.value.status == -3
+    # grids thinner than the stencil along every axis, every schedule
+    for shape in ((3, 5, 9), (1, 1, 1), (2, 70)):
+        t = wi.laplace(shape=shape, so=16, nt=7, seed=1)
+        o = _op(t)
+        got = o.forward(t.nt, torch.from_numpy(t.u0).cuda())
+        assert rel(got.cpu().numpy().astype(np.float64), _oracle(t, t.nt)) <= 1e-5, shape
+        if len(shape) == 3:
+            o.set_schedule(1, 0, 1, 0)
+            assert torch.equal(o.forward(t.nt, torch.from_numpy(t.u0).cuda()), got)

@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs for the acoustic-wave sweep.
+"""Seeded synthetic inputs for the acoustic-wave sweep and the explicit-
+diffusion (Laplace-operator) sweep.
 
 This module only *generates inputs*: velocity models, source wavelets,
 source/receiver coordinates and the geometry of the standard workloads.  It
@@ -214,3 +215,53 @@ def shot_batch(nshots: int = 32, nt: int = 800, seed: int = 5, sizes=None, worke
         with ThreadPoolExecutor(workers) as ex:
             return list(ex.map(one, range(nshots)))
     return [one(i) for i in range(nshots)]
+
+
+# --------------------------------------------------------------------------- Laplace-operator workload
+
+@dataclass
+class DiffWorkload:
+    """Input of the explicit-diffusion sweep (the paper's Laplace-operator
+    workload): grid, spacing, time step, diffusivity, order, steps and the
+    initial field (float32)."""
+    name: str
+    shape: tuple
+    spacing: tuple
+    dt: float
+    alpha: float
+    so: int
+    nt: int
+    u0: np.ndarray
+
+    @property
+    def npts(self):
+        return int(np.prod(self.shape))
+
+
+def laplace_field(shape, seed: int) -> np.ndarray:
+    """Deterministic initial field: a ramp from 1 to 2 over the points in
+    row-major order (the paper's operator listing fills its grid the same
+    way) plus seeded N(0, 0.1^2) noise, so that every point and every tile
+    carries its own values.  float32."""
+    n = int(np.prod(shape))
+    ramp = np.linspace(1.0, 2.0, num=n).reshape(shape)
+    rng = np.random.default_rng(seed)
+    return (ramp + 0.1 * rng.standard_normal(shape)).astype(np.float32)
+
+
+def laplace(n: int = 500, so: int = 8, nt: int = 32, seed: int = 6, shape=None) -> DiffWorkload:
+    """The Laplace-operator workload of the evaluation chapter: an n^3 grid
+    (500^3 x 32 steps and 600^3 x 16 steps there) at space order so, unit
+    spacing and diffusivity.  The time step is 0.9 of 2 h^2 / (a d pi^2),
+    below the stability limit of every order (the symbol of a centred second
+    difference never exceeds pi^2 / h^2 in magnitude), so the field cannot
+    diverge."""
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    nd = len(shape)
+    h, a = 1.0, 1.0
+    dt = 0.9 * 2.0 * h * h / (a * nd * math.pi ** 2)
+    if len(set(shape)) == 1:
+        name = "laplace_%dcube_so%d" % (shape[0], so)
+    else:
+        name = "laplace_%s_so%d" % ("x".join(map(str, shape)), so)
+    return DiffWorkload(name, shape, (h,) * nd, dt, a, so, nt, laplace_field(shape, seed))
