@@ -23,6 +23,9 @@ on one JSON line (progress goes to stderr):
   and gradient through one captured sequence, against the shots one by one;
 * tiling_by_order: the best time-tiled against the best untiled schedule on
   the same 592^3 layered workload at space orders 2, 4 and 8 (100 steps);
+* laplace: the paper's second workload, explicit diffusion on 500^3 x 32
+  and 600^3 x 16 steps at space orders 2..16, default, best untiled and best
+  time-tiled schedule with their algorithmic HBM rates;
 * cpu_baseline: the FP64 oracle on the host cores on a bounded sample.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
@@ -371,6 +374,76 @@ def tiling_factor(so, dev, stream, nt=100, n=512):
             "factor": round(tiled[0] / untiled[0], 3)}
 
 
+def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16)):
+    """The Laplace-operator workload (explicit diffusion) on the paper's grids
+    (500^3 x 32 steps, 600^3 x 16 steps) at space orders 2..16: the default
+    schedule, the best untiled and the best time-tiled schedule (minimum of
+    five runs each), and the algorithmic HBM rate of each (8/T B per
+    point-update)."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import DiffOp, WaveError
+    from paper_1806_08299_amd.wave import wave_bytes_per_point, wave_tiled_max_depth
+    out = []
+    for n, nt in grids:
+        u0 = None
+        for so in orders:
+            w = wi.laplace(n=n, so=so, nt=nt) if u0 is None else None
+            if u0 is None:
+                u0 = torch.from_numpy(w.u0).to(dev)
+                base = w
+            w = wi.DiffWorkload("laplace_%dcube_so%d" % (n, so), base.shape, base.spacing, base.dt, base.alpha,
+                                so, nt, base.u0)
+            op = DiffOp(w.shape, w.spacing, w.dt, w.alpha, w.so, time_tile=0)
+            dflt = op.schedule()
+            res = torch.empty_like(u0)
+
+            def rate(sched):
+                try:
+                    op.set_schedule(*sched)
+                except WaveError:
+                    return 0.0
+                op.forward(nt, u0, res)
+                ts = []
+                for _ in range(5):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    torch.cuda.synchronize()
+                    e0.record(stream)
+                    op.forward(nt, u0, res)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                return w.npts * nt / min(ts) / 1e9
+
+            d_rate = rate((dflt[0], dflt[1], dflt[2], dflt[3]))
+            untiled = max((rate((-1, 0, 0, zc)), zc) for zc in (0, 8, 24))
+            cands = [(T, shape, zc) for shape in (2, 1) for T in range(1, min(4, wave_tiled_max_depth(so, 3, shape)) + 1)
+                     for zc in (0, 4, 8, 16)]
+            tiled = max((rate((T, 0, shape, zc)), (T, shape, zc)) for T, shape, zc in cands)
+            Tb = tiled[1][0]
+
+            def gbs(v, T):
+                return v * 1e9 * wave_bytes_per_point(T, 3) / 1e9
+            out.append({"workload": w.name, "nt": nt, "space_order": so,
+                        "default_schedule": dict(zip(("T", "skew", "tile_shape", "zchunks"), dflt)),
+                        "default": round(d_rate, 1),
+                        "untiled": round(untiled[0], 1), "untiled_zchunks": untiled[1],
+                        "untiled_GBs": round(gbs(untiled[0], -1), 1),
+                        "untiled_frac": round(gbs(untiled[0], -1) / HBM_PEAK_GBS, 4),
+                        "tiled": round(tiled[0], 1),
+                        "tiled_schedule": dict(zip(("T", "tile_shape", "zchunks"), tiled[1])),
+                        "tiled_GBs": round(gbs(tiled[0], Tb), 1),
+                        "tiled_frac": round(gbs(tiled[0], Tb) / HBM_PEAK_GBS, 4),
+                        "factor": round(tiled[0] / untiled[0], 3)})
+            log("laplace %s: default %s %.1f, untiled %.1f, tiled %.1f %s -> %.3fx"
+                % (w.name, dflt, d_rate, untiled[0], tiled[0], tiled[1], out[-1]["factor"]))
+            del op, res
+            torch.cuda.empty_cache()
+        del u0
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,6 +460,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-orders", action="store_true")
+    ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-operator (diffusion) section")
+    ap.add_argument("--laplace-only", action="store_true",
+                    help="diagnostic: run only the Laplace-operator section and print its results")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run plain device copies of known size (reference for the traffic counters)")
     ap.add_argument("--quick", action="store_true", help="small sizes for a functional check")
@@ -407,6 +483,10 @@ def main():
     stream = torch.cuda.current_stream()
     if args.quick:
         args.n, args.nt = 128, 100
+    if args.laplace_only:
+        lap = laplace_bench(dev, stream, grids=((128, 32),) if args.quick else ((500, 32), (600, 16)))
+        print(json.dumps({"laplace": lap}), flush=True)
+        return
 
     # ---------------------------------------------------------------- forward, tuned schedule
     t0 = time.time()
@@ -535,6 +615,9 @@ def main():
             orders.append(tiling_factor(so, dev, stream, n=128 if args.quick else 512))
             log("order %d: untiled %.1f, tiled %.1f %s -> %.3fx" % (so, orders[-1]["untiled"], orders[-1]["tiled"],
                                                                   orders[-1]["tiled_schedule"], orders[-1]["factor"]))
+    lap = None
+    if not args.no_laplace:
+        lap = laplace_bench(dev, stream, grids=((128, 32),) if args.quick else ((500, 32), (600, 16)))
     cpu = None if args.no_cpu else cpu_baseline(w, n=args.n)
 
     line = {
@@ -550,6 +633,7 @@ def main():
         "adjoint_grad": adj,
         "batch": batch,
         "tiling_by_order": orders,
+        "laplace": lap,
         "roofline": roofline,
         "ai": ai,
         "cpu_baseline": cpu,

@@ -374,7 +374,10 @@ struct Plan {
 // time-tiled sweeps want very different counts by depth and order, which
 // wave_autotune finds.
 int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T) {
-  const int64_t target = (kind == KIND_UNTILED) ? (c->dim == 3 ? 32LL : 8LL) * c->num_cu : 2LL * c->num_cu;
+  // time-tiled diffusion (one level per stage, fewer registers): ~6 per CU
+  // (500^3, order 2, depth 4: 8 segments 1481 Gpts/s, 3 segments 1111)
+  const int64_t tiled_per_cu = c->eq == 1 ? 6 : 2;
+  const int64_t target = (kind == KIND_UNTILED) ? (c->dim == 3 ? 32LL : 8LL) * c->num_cu : tiled_per_cu * c->num_cu;
   int64_t zc = (target + base_blocks - 1) / base_blocks;
   const int64_t min_len = (kind == KIND_UNTILED) ? 16 : std::max<int64_t>(16, 4LL * T * c->R);
   zc = std::min<int64_t>(zc, std::max<int64_t>(1, c->n0 / min_len));
@@ -1487,11 +1490,21 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
   char* p = (char*)state;
   c->w[0] = (float*)p;
   c->w[1] = (float*)(p + align_up(sizeof(float) * c->N));
-  // time_tile 0: the untiled sweep (wave_set_schedule picks others)
   s = apply_schedule(c, d->time_tile == 0 ? -1 : d->time_tile, d->skew, d->tile_shape, d->zchunks);
   if (s != WAVE_OK) {
     delete c;
     return s;
+  }
+  if (d->time_tile == 0 && c->dim == 3 && c->R <= 2) {
+    // Default from measurements on MI355X (500^3, 32 steps): depth 4 on
+    // 32 x 64 tiles at radius 1 (3.1x the untiled sweep), depth 2 at radius
+    // 2 (1.9x); from radius 4 on the untiled sweep.
+    const int oshape = c->shape;
+    if (d->tile_shape == 0) c->shape = 2;
+    const int T = c->R == 1 ? 4 : 2;
+    Plan pl;
+    if (make_plan(c, KIND_TILED, T, pl) == WAVE_OK) c->T = T;
+    else c->shape = oshape;
   }
   c->err.clear();
   *out = c;

@@ -108,3 +108,19 @@ def test_diffusion_edge_cases():
         if len(shape) == 3:
             o.set_schedule(1, 0, 1, 0)
             assert torch.equal(o.forward(t.nt, torch.from_numpy(t.u0).cuda()), got)
+
+
+@pytest.mark.parametrize("so,expect", [(2, 4), (4, 2), (8, -1), (16, -1)])
+def test_diffusion_default_schedule(so, expect):
+    """time_tile = 0: depth 4 (radius 1) or 2 (radius 2) on 32x64 tiles in
+    3D, untiled otherwise; bitwise the untiled result."""
+    w = wi.laplace(shape=(40, 50, 130), so=so, nt=9, seed=2)
+    op = _op(w, time_tile=0)
+    T, skew, tshape, _ = op.schedule()
+    assert T == expect and skew == so // 2
+    if T > 0:
+        assert tshape == 2
+    u0 = torch.from_numpy(w.u0).cuda()
+    got = op.forward(w.nt, u0)
+    op.set_schedule(-1, 0, 0, 0)
+    assert torch.equal(got, op.forward(w.nt, u0))
