@@ -110,7 +110,9 @@ wave_status wave_get_schedule(const wave_ctx* ctx, int32_t* time_tile, int32_t* 
  * checkpoints followed by wave_adjoint_grad (adjoint = 1), or by one shot of
  * wave_batch with a gradient (adjoint = 2: also the residual traces) for nt
  * steps with nsrc sources and nrec receivers; ckpt_every = K > 0 keeps a
- * checkpoint of (u^{cK}, u^{cK-1}) for every segment. */
+ * checkpoint of (u^{cK}, u^{cK-1}) for every segment.  On a diffusion
+ * context: the scratch wave_autotune needs (2 N floats), whatever the
+ * arguments. */
 size_t wave_scratch_bytes(const wave_ctx* ctx, int32_t nt, int32_t nsrc, int32_t nrec, int32_t ckpt_every,
                           int32_t adjoint);
 
@@ -187,7 +189,10 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
  * candidate): first every depth T <= max_T and tile shape at the default
  * number of axis-0 segments, then 1..32 axis-0 segments for the five fastest.
  * Keeps the fastest.  Synchronises; needs scratch for `trial_steps` forward
- * steps without sources. */
+ * steps without sources (wave_scratch_bytes(ctx, trial_steps, 0, 0, 0, 0)).
+ * On a diffusion context (diff_init) the trials are diff_forward calls from
+ * a zero field between two levels in the scratch (2 N floats, also what
+ * wave_scratch_bytes returns for such a context). */
 wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
                           void* scratch_dev, size_t scratch_bytes, double* best_seconds_per_step);
 

@@ -918,6 +918,7 @@ void wave_destroy(wave_ctx* c) {
 
 size_t wave_scratch_bytes(const wave_ctx* c, int32_t nt, int32_t nsrc, int32_t nrec, int32_t K, int32_t adjoint) {
   if (!c || nt < 0 || nsrc < 0 || nrec < 0 || K < 0) return 0;
+  if (c->eq == 1) return 2 * align_up(sizeof(float) * c->N);   // diffusion: wave_autotune's two levels
   return layout(c, nt, nsrc, nrec, K, adjoint).total;
 }
 
@@ -1256,11 +1257,19 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const 
 wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, void* scratch,
                           size_t scratch_bytes, double* best) {
   if (!c || trial_steps < 1 || repeats < 1) return WAVE_EINVAL;
-  if (c->eq != 0) return fail(c, WAVE_ESTATE, "not a wave-equation context");
-  const Layout L = layout(c, trial_steps, 0, 0, 0, 0);
-  if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  // Wave equation: trial forwards with the scratch layout of wave_forward.
+  // Diffusion: trial diff_forward calls from a zero field in the first half
+  // of the scratch into its second half.
+  const bool diff = c->eq == 1;
+  const Layout L = diff ? Layout{} : layout(c, trial_steps, 0, 0, 0, 0);
+  const size_t level = align_up(sizeof(float) * c->N);
+  if (!scratch || scratch_bytes < (diff ? 2 * level : L.total)) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
   c->gen++;
   c->ck.valid = false;   // the trial sweeps overwrite the state (and perhaps the scratch)
+  if (diff) {
+    wave_status fs = fill(c, (float*)scratch, c->N, 0.0f);
+    if (fs != WAVE_OK) return fs;
+  }
   struct Cand { int T, skew, shape, zc; };
   std::vector<Cand> cands;
   cands.push_back({-1, c->R, c->shape ? c->shape : 1, 0});
@@ -1279,9 +1288,11 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
     double tmin = 1e300;
     for (int r = 0; r < repeats + 1; ++r) {
       hipEventRecord(e0, c->stream);
-      if (forward_core(c, trial_steps, 0, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, (char*)scratch,
-                       L) != WAVE_OK)
-        return 1e300;
+      const wave_status st =
+          diff ? diff_forward(c, trial_steps, (const float*)scratch, (float*)((char*)scratch + level))
+               : forward_core(c, trial_steps, 0, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0,
+                              (char*)scratch, L);
+      if (st != WAVE_OK) return 1e300;
       hipEventRecord(e1, c->stream);
       if (hipEventSynchronize(e1) != hipSuccess) return 1e300;
       float ms = 0;

@@ -496,6 +496,13 @@ class DiffOp:
     def schedule(self):
         return wave_get_schedule(self.ctx)
 
+    def autotune(self, trial_steps: int = 8, repeats: int = 2, max_T: int = 0) -> float:
+        """Time the schedules (wave_autotune) and keep the fastest; returns
+        its seconds per step."""
+        sc = torch.empty(max(256, wave_scratch_bytes(self.ctx, trial_steps, 0, 0)), dtype=torch.uint8,
+                         device=self.device)
+        return wave_autotune(self.ctx, trial_steps, repeats, max_T, sc)
+
     def forward(self, nt: int, u0: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         u0 = u0.to(self.device, torch.float32).contiguous()
         if tuple(u0.shape) != self.shape:

@@ -124,3 +124,17 @@ def test_diffusion_default_schedule(so, expect):
     got = op.forward(w.nt, u0)
     op.set_schedule(-1, 0, 0, 0)
     assert torch.equal(got, op.forward(w.nt, u0))
+
+
+def test_diffusion_autotune():
+    """wave_autotune on a diffusion context picks a valid schedule whose
+    result is bitwise the untiled sweep's."""
+    w = wi.laplace(shape=(64, 96, 200), so=2, nt=10, seed=8)
+    op = _op(w)
+    u0 = torch.from_numpy(w.u0).cuda()
+    ref = op.forward(w.nt, u0)
+    per_step = op.autotune(trial_steps=8, repeats=1)
+    assert 0 < per_step < 1.0
+    T, skew, shape, zc = op.schedule()
+    assert T == -1 or 1 <= T <= 6
+    assert torch.equal(op.forward(w.nt, u0), ref)
