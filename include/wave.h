@@ -77,7 +77,7 @@ typedef struct wave_desc {
   int32_t tile_shape;    /* 3D tiled sweep: 0 = auto; 1 = 64x64 extended tile;
                             2 = 32x64 extended tile (both 512 threads).  2D: ignored */
   int32_t zchunks;       /* segments of axis 0 per launch; 0 = auto (untiled 3D: about
-                            32 workgroups per CU, segments of at least 16 planes) */
+                            32 workgroups per CU, segments of at least max(16, 4r) planes) */
 } wave_desc;
 
 typedef struct wave_ctx wave_ctx;

@@ -379,7 +379,9 @@ int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T) {
   const int64_t tiled_per_cu = c->eq == 1 ? 6 : 2;
   const int64_t target = (kind == KIND_UNTILED) ? (c->dim == 3 ? 32LL : 8LL) * c->num_cu : tiled_per_cu * c->num_cu;
   int64_t zc = (target + base_blocks - 1) / base_blocks;
-  const int64_t min_len = (kind == KIND_UNTILED) ? 16 : std::max<int64_t>(16, 4LL * T * c->R);
+  // A segment re-reads 2R planes of window fill: keep it at least 4R long.
+  const int64_t min_len = (kind == KIND_UNTILED) ? std::max<int64_t>(16, 4LL * c->R)
+                                                 : std::max<int64_t>(16, 4LL * T * c->R);
   zc = std::min<int64_t>(zc, std::max<int64_t>(1, c->n0 / min_len));
   return (int)std::max<int64_t>(1, zc);
 }
