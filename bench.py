@@ -386,12 +386,9 @@ def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16
     from paper_1806_08299_amd.wave import wave_bytes_per_point, wave_tiled_max_depth
     out = []
     for n, nt in grids:
-        u0 = None
+        base = wi.laplace(n=n, so=orders[0], nt=nt)   # the field is the same at every order
+        u0 = torch.from_numpy(base.u0).to(dev)
         for so in orders:
-            w = wi.laplace(n=n, so=so, nt=nt) if u0 is None else None
-            if u0 is None:
-                u0 = torch.from_numpy(w.u0).to(dev)
-                base = w
             w = wi.DiffWorkload("laplace_%dcube_so%d" % (n, so), base.shape, base.spacing, base.dt, base.alpha,
                                 so, nt, base.u0)
             op = DiffOp(w.shape, w.spacing, w.dt, w.alpha, w.so, time_tile=0)
@@ -439,7 +436,7 @@ def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16
                 % (w.name, dflt, d_rate, untiled[0], tiled[0], tiled[1], out[-1]["factor"]))
             del op, res
             torch.cuda.empty_cache()
-        del u0
+        del u0, base
         torch.cuda.empty_cache()
     return out
 
