@@ -1508,15 +1508,18 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
     delete c;
     return s;
   }
-  if (d->time_tile == 0 && c->dim == 3 && c->R <= 2) {
-    // Default from measurements on MI355X (500^3, 32 steps): depth 4 on
-    // 32 x 64 tiles at radius 1 (3.1x the untiled sweep), depth 2 at radius
-    // 2 (1.9x); from radius 4 on the untiled sweep.
+  // Default from measurements on MI355X (32 steps): 3D (500^3) depth 4 on
+  // 32 x 64 tiles at radius 1 (3.1x the untiled sweep), depth 2 at radius 2
+  // (2.0x), untiled from radius 4; 2D (16384^2) depth 4 up to radius 2
+  // (3.3x, 2.7x), depth 2 up to radius 4 (1.7x), untiled beyond.
+  int Td = 0;
+  if (c->dim == 3) Td = c->R == 1 ? 4 : (c->R == 2 ? 2 : 0);
+  else Td = c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0);
+  if (d->time_tile == 0 && Td > 0) {
     const int oshape = c->shape;
-    if (d->tile_shape == 0) c->shape = 2;
-    const int T = c->R == 1 ? 4 : 2;
+    if (c->dim == 3 && d->tile_shape == 0) c->shape = 2;
     Plan pl;
-    if (make_plan(c, KIND_TILED, T, pl) == WAVE_OK) c->T = T;
+    if (make_plan(c, KIND_TILED, Td, pl) == WAVE_OK) c->T = Td;
     else c->shape = oshape;
   }
   c->err.clear();

@@ -110,15 +110,18 @@ def test_diffusion_edge_cases():
             assert torch.equal(o.forward(t.nt, torch.from_numpy(t.u0).cuda()), got)
 
 
-@pytest.mark.parametrize("so,expect", [(2, 4), (4, 2), (8, -1), (16, -1)])
-def test_diffusion_default_schedule(so, expect):
-    """time_tile = 0: depth 4 (radius 1) or 2 (radius 2) on 32x64 tiles in
-    3D, untiled otherwise; bitwise the untiled result."""
-    w = wi.laplace(shape=(40, 50, 130), so=so, nt=9, seed=2)
+@pytest.mark.parametrize("so,shape,expect", [(2, (40, 50, 130), 4), (4, (40, 50, 130), 2), (8, (40, 50, 130), -1),
+                                            (16, (40, 50, 130), -1), (2, (60, 2100), 4), (8, (60, 2100), 2),
+                                            (16, (60, 2100), -1)])
+def test_diffusion_default_schedule(so, shape, expect):
+    """time_tile = 0: 3D depth 4 (radius 1) or 2 (radius 2) on 32x64 tiles;
+    2D depth 4 up to radius 2, 2 up to radius 4; untiled otherwise; bitwise
+    the untiled result."""
+    w = wi.laplace(shape=shape, so=so, nt=9, seed=2)
     op = _op(w, time_tile=0)
     T, skew, tshape, _ = op.schedule()
     assert T == expect and skew == so // 2
-    if T > 0:
+    if T > 0 and len(shape) == 3:
         assert tshape == 2
     u0 = torch.from_numpy(w.u0).cuda()
     got = op.forward(w.nt, u0)
