@@ -166,10 +166,13 @@ wave_status wave_adjoint_grad(wave_ctx* ctx, int32_t nt,
  *   dobs_dev     device [nt][nrec] observed traces (with grad_m_dev only)
  *   scratch_dev  device, scratch_bytes[i] >= wave_scratch_bytes(ctx_i, nt,
  *                nsrc_i, nrec_i, ckpt_every if gradient else 0, 2 if gradient else 0)
- * Each shot's operations are recorded and the pending sweeps of all shots
- * are merged: one launch per group of shots with equal (radius, depth,
- * dim, tile shape, mode), at most 12 shots per launch, each workgroup
- * finding its shot from the launch arguments.  The merged sequence is
+ * Each shot's operations are recorded and the pending sweeps of the shots
+ * are merged in lockstep: one launch per group of shots with equal (radius,
+ * depth, dim, tile shape, mode), at most 12 shots per launch, each workgroup
+ * finding its shot from the launch arguments.  A gradient batch merges all
+ * shots; a forward-only batch merges consecutive shots up to 96 MiB of
+ * per-step working set and runs those groups one after another (cache
+ * locality between steps).  The merged sequence is
  * captured into a HIP graph and launched; a later call with the same
  * arguments on contexts that no other call has touched since replays that
  * graph without recording again (device inputs may change in between).

@@ -1076,6 +1076,14 @@ wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const doubl
 // pending sweeps of all shots are merged, one launch per group of equal
 // (radius, kind, depth, dim, mode, shape), at most kMaxBatch shots each.  A
 // group of one uses the single-context kernel.
+// Forward-only batches merge shots in lockstep within groups of at most this
+// many bytes of per-step working set (16 B per point), run one group after
+// another: the 256 MiB last-level cache then keeps a group's levels between
+// steps.  On the 32-shot workload that is 0.998x the shots run one by one
+// against 0.977x for one lockstep group.  Gradient batches keep one group:
+// merging all shots' many small launches wins there (1.08x against 1.02x).
+constexpr size_t kBatchGroupBytes = size_t(96) << 20;
+
 static wave_status replay_merged(wave_ctx* lead, std::vector<Recorder>& recs, hipStream_t st) {
   const size_t n = recs.size();
   std::vector<size_t> pos(n, 0);
@@ -1237,7 +1245,23 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const 
   // table uploads made there during recording.
   if (!lead->cap) HIP_TRY(lead, hipStreamCreateWithFlags(&lead->cap, hipStreamNonBlocking));
   HIP_TRY(lead, hipStreamBeginCapture(lead->cap, hipStreamCaptureModeRelaxed));
-  s = replay_merged(lead, recs, lead->cap);
+  {
+    std::vector<std::vector<Recorder>> groups;
+    size_t acc = 0;
+    for (int i = 0; i < nshots; ++i) {
+      const size_t ws = 16u * (size_t)ctxs[i]->N;
+      if (groups.empty() || (!grad && acc + ws > kBatchGroupBytes)) {
+        groups.emplace_back();
+        acc = 0;
+      }
+      groups.back().push_back(std::move(recs[i]));
+      acc += ws;
+    }
+    for (auto& g : groups) {
+      s = replay_merged(lead, g, lead->cap);
+      if (s != WAVE_OK) break;
+    }
+  }
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(lead->cap, &g);
   if (s != WAVE_OK) {
