@@ -70,14 +70,16 @@ typedef struct wave_desc {
   int32_t nbl;           /* absorbing-layer width in points; 0 = no damping */
   double sigma_max;      /* damping maximum in 1/s (ignored if nbl == 0) */
   int32_t time_tile;     /* T >= 1 fused steps per launch; -1 = untiled single-step
-                            sweep (the reference schedule); 0 = default: T = 3 on
-                            32x64 tiles at radius 1 in 3D, untiled otherwise (the
-                            measured best on MI355X; wave_autotune refines by timing) */
+                            sweep (the reference schedule); 0 = default: 3D T = 3 on
+                            32x64 tiles at radius 1; 2D T = 4 up to radius 2, T = 2 up
+                            to radius 4; untiled otherwise (the measured best on
+                            MI355X; wave_autotune refines by timing) */
   int32_t skew;          /* halo per fused step on the tiled axes; 0 = r; must be >= r */
   int32_t tile_shape;    /* 3D tiled sweep: 0 = auto; 1 = 64x64 extended tile;
                             2 = 32x64 extended tile (both 512 threads).  2D: ignored */
   int32_t zchunks;       /* segments of axis 0 per launch; 0 = auto (untiled 3D: about
-                            32 workgroups per CU, segments of at least max(16, 4r) planes) */
+                            32 workgroups per CU, segments of at least max(16, 4r) planes;
+                            time-tiled 2D: about 16 per CU) */
 } wave_desc;
 
 typedef struct wave_ctx wave_ctx;

@@ -375,8 +375,10 @@ struct Plan {
 // wave_autotune finds.
 int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T) {
   // time-tiled diffusion (one level per stage, fewer registers): ~6 per CU
-  // (500^3, order 2, depth 4: 8 segments 1481 Gpts/s, 3 segments 1111)
-  const int64_t tiled_per_cu = c->eq == 1 ? 6 : 2;
+  // (500^3, order 2, depth 4: 8 segments 1481 Gpts/s, 3 segments 1111).
+  // 2D (a row of 1 x 1024 tiles per plane): ~16 per CU (16384^2 wave,
+  // order 4, depth 4: 256 segments 643 Gpts/s against 469 with 31).
+  const int64_t tiled_per_cu = c->dim == 2 ? 16 : (c->eq == 1 ? 6 : 2);
   const int64_t target = (kind == KIND_UNTILED) ? (c->dim == 3 ? 32LL : 8LL) * c->num_cu : tiled_per_cu * c->num_cu;
   int64_t zc = (target + base_blocks - 1) / base_blocks;
   // A segment re-reads 2R planes of window fill: keep it at least 4R long.
@@ -892,12 +894,15 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
     // on the time-tiled sweep wins only with a tuned segment count (radius
     // 2) or not at all, so the untiled sweep is the default.  wave_autotune
     // refines by timing on the actual problem.
+    // 2D (16384^2, 100 steps): depth 4 up to radius 2 (2.8x, 2.3x), depth
+    // 2 up to radius 4 (1.4x), untiled beyond.
     int best = -1;
-    if (c->dim == 3 && c->R <= 1) {
+    const int Td = c->dim == 3 ? (c->R <= 1 ? 3 : 0) : (c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0));
+    if (Td > 0) {
       const int oshape = c->shape;
-      if (d->tile_shape == 0) c->shape = 2;
+      if (c->dim == 3 && d->tile_shape == 0) c->shape = 2;
       Plan pl;
-      if (make_plan(c, KIND_TILED, 3, pl) == WAVE_OK) best = 3;
+      if (make_plan(c, KIND_TILED, Td, pl) == WAVE_OK) best = Td;
       else c->shape = oshape;
     }
     c->T = best;
