@@ -20,7 +20,10 @@ properties are checked instead:
   while any wrong term (an O(1) change) fails;
 * gradient problem: the FP32 dot-product test <F q, dd> = <q, F^T dd> over
   2000 steps within 1e-4, and the gradient bitwise independent of the
-  checkpoint interval and of the schedule (untiled vs time-tiled adjoint).
+  checkpoint interval and of the schedule (untiled vs time-tiled adjoint);
+* the Laplace-operator workload (explicit diffusion) at 500^3, orders 2 and
+  8: the bench's time-tiled launch configurations bitwise equal to the
+  untiled sweep, and one further step against the FP64 oracle (1e-6).
 """
 import numpy as np
 import pytest
@@ -107,3 +110,32 @@ def test_full_size_gradient_dot_product_and_schedule_independence():
         torch.cuda.synchronize()
         assert torch.equal(gm2, gm), (T, shape, K)
         del gm2
+
+
+@pytest.mark.parametrize("so,scheds", [(2, [(4, 2, 8), (4, 2, 0), (2, 2, 32)]), (8, [(1, 2, 4), (2, 2, 0)])])
+def test_full_size_diffusion(so, scheds):
+    """The Laplace-operator workload at the paper's 500^3 grid: the bench's
+    time-tiled launch configurations bitwise equal to the untiled sweep over
+    8 steps, then one more step against one FP64 oracle step over the whole
+    grid (relative L2 1e-6, the bound argued above for one step)."""
+    from paper_1806_08299_amd import DiffOp
+    w = wi.laplace(n=500, so=so, nt=8)
+    op = DiffOp(w.shape, w.spacing, w.dt, w.alpha, w.so)
+    u0 = torch.from_numpy(w.u0).cuda()
+    print("full-size diffusion so%d: untiled" % so, flush=True)
+    ref = op.forward(w.nt, u0)
+    torch.cuda.synchronize()
+    for T, shape, zc in scheds:
+        print("full-size diffusion so%d: T=%d shape=%d zc=%d" % (so, T, shape, zc), flush=True)
+        op.set_schedule(T, 0, shape, zc)
+        assert torch.equal(op.forward(w.nt, u0), ref), (T, shape, zc)
+    op.set_schedule(-1, 0, 0, 0)
+    one = op.forward(1, ref).cpu().numpy().astype(np.float64)
+    state = ref.cpu().numpy().astype(np.float64)
+    del ref, u0
+    torch.cuda.empty_cache()
+    g = oracle.Grid(w.shape, w.spacing, w.dt, w.so)
+    expect = oracle.diffuse(g, w.alpha, 1, state)
+    err = np.linalg.norm(one - expect) / np.linalg.norm(expect)
+    print("full-size diffusion so%d: one-step relative L2 %.3e" % (so, err), flush=True)
+    assert err <= 1e-6
