@@ -309,9 +309,11 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
   float zw[RY][W];
   // NP sets of prefetch registers: plane z's loads are issued NP planes
   // ahead, into the set that iteration z consumes (no register moves).
-  // Diffusion (one input stream, few registers) gains 3-4 % from two planes
-  // in flight; the wave sweeps measured equal and keep one.
-  constexpr int NP = DF ? 2 : 1;
+  // Two planes in flight pay where a point reads few inputs for its
+  // registers or many streams: diffusion +3-4 %, the recompute storing the
+  // history and the adjoint with imaging -5 % time; the plain wave forward
+  // measured equal and keeps one.
+  constexpr int NP = (MODE == MODE_FWD) ? 1 : 2;
   static_assert(NP == 1 || !ROT, "a two-plane prefetch needs the shifted window");
   float pc[NP][RY], pp[NP][RY], pb[NP][RY], ph[NP][HPT];
   {
