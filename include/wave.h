@@ -237,7 +237,8 @@ double wave_bytes_per_point(int32_t time_tile, int32_t mode);
 
 /* ------------------------------------------------------------------------
  * Explicit diffusion: the Laplace-operator workload of the paper's evaluation
- * chapter (first order in time, one time dependency).  The paper never prints
+ * chapter (Evaluation, Performance of the Laplace operator: first order in
+ * time, one time dependency).  The paper never prints
  * its equation; it is read as
  *     u^{n+1} = u^n + dt a (L u^n)
  * with the Laplacian, coefficients and zero ghosts of the wave sweep above
@@ -259,7 +260,8 @@ typedef struct diff_desc {
                             otherwise -- the measured best on MI355X) */
   int32_t skew;          /* 0 = r; must be >= r */
   int32_t tile_shape;    /* as in wave_desc */
-  int32_t zchunks;       /* as in wave_desc; 0 = auto (time-tiled: about 6 workgroups per CU) */
+  int32_t zchunks;       /* as in wave_desc; 0 = auto (time-tiled: about 6 workgroups per CU
+                            in 3D, 16 in 2D) */
 } diff_desc;
 
 /* Flops per point-update of explicit diffusion (FMA = 2). Host-only. */
@@ -270,8 +272,9 @@ size_t diff_state_bytes(const diff_desc* d);
 
 /* Validate `d` (as wave_desc, plus alpha > 0 finite) and the stability limit
  * dt a sum_a rho / h_a^2 <= 2 (rho as for wave_init), and carve the state.
- * The context takes wave_set_schedule, wave_get_schedule, wave_last_error
- * and wave_destroy; the wave-equation calls reject it with WAVE_ESTATE.
+ * The context takes wave_set_schedule, wave_get_schedule, wave_autotune,
+ * wave_scratch_bytes, wave_last_error and wave_destroy; the wave-equation
+ * calls reject it with WAVE_ESTATE.
  * Errors: WAVE_EINVAL, WAVE_ESKEW, WAVE_ECFL, WAVE_ENOMEM, WAVE_EUNSUPPORTED. */
 wave_status diff_init(const diff_desc* d, void* state_dev, size_t state_bytes, void* hip_stream,
                       wave_ctx** out);
