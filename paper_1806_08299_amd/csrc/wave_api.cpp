@@ -1539,10 +1539,11 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
   }
   // Default from measurements on MI355X (32 steps): 3D (500^3) depth 4 on
   // 32 x 64 tiles at radius 1 (3.1x the untiled sweep), depth 2 at radius 2
-  // (2.0x), untiled from radius 4; 2D (16384^2) depth 4 up to radius 2
-  // (3.3x, 2.7x), depth 2 up to radius 4 (1.7x), untiled beyond.
+  // (2.0x), the depth-1 tiled sweep on 32 x 64 tiles up to radius 4 (1.1x),
+  // untiled beyond; 2D (16384^2) depth 4 up to radius 2 (3.3x, 2.7x),
+  // depth 2 up to radius 4 (1.7x), untiled beyond.
   int Td = 0;
-  if (c->dim == 3) Td = c->R == 1 ? 4 : (c->R == 2 ? 2 : 0);
+  if (c->dim == 3) Td = c->R == 1 ? 4 : (c->R == 2 ? 2 : (c->R <= 4 ? 1 : 0));
   else Td = c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0);
   if (d->time_tile == 0 && Td > 0) {
     const int oshape = c->shape;

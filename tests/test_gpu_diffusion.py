@@ -110,11 +110,12 @@ def test_diffusion_edge_cases():
             assert torch.equal(o.forward(t.nt, torch.from_numpy(t.u0).cuda()), got)
 
 
-@pytest.mark.parametrize("so,shape,expect", [(2, (40, 50, 130), 4), (4, (40, 50, 130), 2), (8, (40, 50, 130), -1),
+@pytest.mark.parametrize("so,shape,expect", [(2, (40, 50, 130), 4), (4, (40, 50, 130), 2), (8, (40, 50, 130), 1),
                                             (16, (40, 50, 130), -1), (2, (60, 2100), 4), (8, (60, 2100), 2),
                                             (16, (60, 2100), -1)])
 def test_diffusion_default_schedule(so, shape, expect):
-    """time_tile = 0: 3D depth 4 (radius 1) or 2 (radius 2) on 32x64 tiles;
+    """time_tile = 0: 3D depth 4 (radius 1), 2 (radius 2) or 1 (up to radius
+    4) on 32x64 tiles;
     2D depth 4 up to radius 2, 2 up to radius 4; untiled otherwise; bitwise
     the untiled result."""
     w = wi.laplace(shape=shape, so=so, nt=9, seed=2)
