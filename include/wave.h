@@ -96,7 +96,9 @@ size_t wave_state_bytes(const wave_desc* d);
 wave_status wave_init(const wave_desc* d, const float* m_dev, void* state_dev, size_t state_bytes,
                       void* hip_stream, wave_ctx** out);
 
-/* Replace the model (same shape); re-checks the CFL limit (synchronises). */
+/* Replace the model (same shape); re-checks the CFL limit (synchronises).
+ * Every entry must be a positive finite number (WAVE_EINVAL otherwise,
+ * NaN included). */
 wave_status wave_set_model(wave_ctx* ctx, const float* m_dev);
 
 /* Change the schedule of an existing context: T >= 1 or -1 (untiled), skew
@@ -141,7 +143,7 @@ wave_status wave_forward(wave_ctx* ctx, int32_t nt,
  *                   keeps the whole history)
  *   reuse           1: use the checkpoints of the immediately preceding
  *                   wave_forward on this context and scratch (same nt, K,
- *                   sources and wavelet buffer, model unchanged since:
+ *                   sources, receiver count and wavelet buffer, model unchanged since:
  *                   wave_set_model and every other sweep discard them; else
  *                   WAVE_ESTATE); the wavelet's contents must not have
  *                   changed either; 0: run that forward here.
@@ -281,7 +283,7 @@ wave_status diff_init(const diff_desc* d, void* state_dev, size_t state_bytes, v
                       wave_ctx** out);
 
 /* nt steps from u0_dev [N] (device, read only) into u_out_dev [N] (device);
- * the two must not overlap.  Intermediate levels live in the state.  nt == 0
+ * the two must not overlap each other or the context's state (WAVE_EINVAL).  Intermediate levels live in the state.  nt == 0
  * copies.  Asynchronous on the context's stream.  Errors: WAVE_EINVAL,
  * WAVE_ESTATE (not a diffusion context), WAVE_EUNSUPPORTED, WAVE_EHIP. */
 wave_status diff_forward(wave_ctx* ctx, int32_t nt, const float* u0_dev, float* u_out_dev);

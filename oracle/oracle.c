@@ -255,9 +255,10 @@ int og_forward(const og_grid *g, const double *m, int nt,
     double *c = (double *)calloc(N, sizeof(double)); /* u^{n+1} */
     double *lap = (double *)malloc(N * sizeof(double));
     double *inj = (double *)calloc(N, sizeof(double));
-    og_pts S, R;
-    if (!sig || !a || !b || !c || !lap || !inj) return -1;
-    if (og_pts_make(g, nsrc, src_xyz, &S) || og_pts_make(g, nrec, rec_xyz, &R)) return -1;
+    og_pts S = {0, NULL, NULL, NULL}, R = {0, NULL, NULL, NULL};
+    int rc = -1;
+    if (!sig || !a || !b || !c || !lap || !inj) goto done;
+    if (og_pts_make(g, nsrc, src_xyz, &S) || og_pts_make(g, nrec, rec_xyz, &R)) goto done;
     og_sigma(g, sig);
     if (u_init) {
         memcpy(b, u_init, N * sizeof(double));
@@ -292,6 +293,8 @@ int og_forward(const og_grid *g, const double *m, int nt,
         memcpy(u_final, b, N * sizeof(double));
         memcpy(u_final + N, a, N * sizeof(double));
     }
+    rc = 0;
+done: /* every exit releases what was allocated */
     og_pts_free(&S);
     og_pts_free(&R);
     free(sig);
@@ -300,7 +303,7 @@ int og_forward(const og_grid *g, const double *m, int nt,
     free(c);
     free(lap);
     free(inj);
-    return 0;
+    return rc;
 }
 
 /*
@@ -327,9 +330,10 @@ int og_adjoint(const og_grid *g, const double *m, int nt,
     double *c = (double *)calloc(N, sizeof(double)); /* mu^n */
     double *lap = (double *)malloc(N * sizeof(double));
     double *inj = (double *)calloc(N, sizeof(double));
-    og_pts S, R;
-    if (!sig || !a || !b || !c || !lap || !inj) return -1;
-    if (og_pts_make(g, nsrc, src_xyz, &S) || og_pts_make(g, nrec, rec_xyz, &R)) return -1;
+    og_pts S = {0, NULL, NULL, NULL}, R = {0, NULL, NULL, NULL};
+    int rc = -1;
+    if (!sig || !a || !b || !c || !lap || !inj) goto done;
+    if (og_pts_make(g, nsrc, src_xyz, &S) || og_pts_make(g, nrec, rec_xyz, &R)) goto done;
     og_sigma(g, sig);
     double dt2 = g->dt * g->dt;
     if (grad_m) memset(grad_m, 0, N * sizeof(double));
@@ -376,6 +380,8 @@ int og_adjoint(const og_grid *g, const double *m, int nt,
         memcpy(mu_final, b, N * sizeof(double));
         memcpy(mu_final + N, a, N * sizeof(double));
     }
+    rc = 0;
+done: /* every exit releases what was allocated */
     og_pts_free(&S);
     og_pts_free(&R);
     free(sig);
@@ -384,7 +390,7 @@ int og_adjoint(const og_grid *g, const double *m, int nt,
     free(c);
     free(lap);
     free(inj);
-    return 0;
+    return rc;
 }
 
 /* Explicit diffusion, the paper's Laplace-operator family: nt steps of

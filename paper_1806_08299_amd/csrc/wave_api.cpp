@@ -788,33 +788,56 @@ wave_status wave_get_schedule(const wave_ctx* c, int32_t* T, int32_t* skew, int3
   return WAVE_OK;
 }
 
-// min(m) on the device, one float back to the host.
+// Per block: the minimum of m and the number of entries that are not
+// positive finite numbers (NaN included), as two floats out[2 blk], out[2 blk + 1].
 __global__ void k_min_reduce(const float* m, int64_t n, float* out) {
   __shared__ float sh[256];
-  float v = 3.4e38f;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    v = fminf(v, m[i]);
+  __shared__ float bad[256];
+  float v = 3.4e38f, nb = 0.0f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = m[i];
+    v = fminf(v, x);
+    nb += (x > 0.0f && x <= 3.4028234e38f) ? 0.0f : 1.0f;   // false for NaN and +inf
+  }
   sh[threadIdx.x] = v;
+  bad[threadIdx.x] = nb;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] = fminf(sh[threadIdx.x], sh[threadIdx.x + s]);
+    if ((int)threadIdx.x < s) {
+      sh[threadIdx.x] = fminf(sh[threadIdx.x], sh[threadIdx.x + s]);
+      bad[threadIdx.x] += bad[threadIdx.x + s];
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = sh[0];
+    out[2 * blockIdx.x + 1] = bad[0];
+  }
 }
 
 wave_status wave_set_model(wave_ctx* c, const float* m) {
   if (!c || !m) return fail(c, WAVE_EINVAL, "null model");
   if (c->eq != 0) return fail(c, WAVE_ESTATE, "not a wave-equation context");
-  // min(m) via the wavefield buffer w[3] as temporary space (overwritten by any sweep anyway)
-  const int nb = 1024;
+  // min(m) and a count of invalid entries, through the wavefield buffer w[3]
+  // as temporary space (overwritten by any sweep anyway).  One block per 256
+  // points (at most 1024): the 2 nb floats written never pass the end of w[3]
+  // (2 ceil(N/256) <= N for N > 64; at least 64 floats in the aligned region
+  // otherwise).
+  const int nb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (c->N + 255) / 256));
+  if (2 * (size_t)nb * sizeof(float) > align_up(sizeof(float) * (size_t)c->N))
+    return fail(c, WAVE_EINVAL, "internal: model reduction larger than its buffer");
   hipLaunchKernelGGL(k_min_reduce, dim3(nb), dim3(256), 0, c->stream, m, c->N, c->w[3]);
   HIP_TRY(c, hipGetLastError());
-  std::vector<float> mins(nb);
-  HIP_TRY(c, hipMemcpyAsync(mins.data(), c->w[3], nb * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  std::vector<float> part(2 * (size_t)nb);
+  HIP_TRY(c, hipMemcpyAsync(part.data(), c->w[3], part.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  float mn = *std::min_element(mins.begin(), mins.end());
-  if (!(mn > 0.0f) || !std::isfinite(mn)) return fail(c, WAVE_EINVAL, "model must be positive and finite");
+  float mn = 3.4e38f, nbad = 0.0f;
+  for (int i = 0; i < nb; ++i) {
+    mn = std::min(mn, part[2 * (size_t)i]);
+    nbad += part[2 * (size_t)i + 1];
+  }
+  if (nbad != 0.0f || !(mn > 0.0f) || !std::isfinite(mn))
+    return fail(c, WAVE_EINVAL, "model must be positive and finite everywhere");
   const double cmax = 1.0 / std::sqrt((double)mn);
   const double cfl = cfl_number(&c->d, cmax);
   if (cfl > 1.0 + 1e-12) {
@@ -1062,7 +1085,8 @@ wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const doubl
   if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
   char* sc = (char*)scratch;
   if (reuse) {
-    const bool ok = c->ck.valid && c->ck.nt == nt && c->ck.K == K && c->ck.nsrc == nsrc && c->ck.scratch == scratch &&
+    const bool ok = c->ck.valid && c->ck.nt == nt && c->ck.K == K && c->ck.nsrc == nsrc && c->ck.nrec == nrec &&
+                    c->ck.scratch == scratch &&
                     c->ck.wavelet == wav &&
                     std::equal(c->ck.src.begin(), c->ck.src.end(), src);
     if (!ok) return fail(c, WAVE_ESTATE, "no matching checkpoints from a preceding forward");
@@ -1563,7 +1587,18 @@ wave_status diff_forward(wave_ctx* c, int32_t nt, const float* u0, float* u_out)
   if (c->eq != 1) return fail(c, WAVE_ESTATE, "not a diffusion context");
   if (nt < 0) return fail(c, WAVE_EINVAL, "negative nt");
   if (!u0 || !u_out) return fail(c, WAVE_EINVAL, "null field");
-  if (u0 == u_out) return fail(c, WAVE_EINVAL, "u_out must not alias u0");
+  // One launch reads its input while other workgroups write its output, so
+  // no two of u0, u_out and the two state levels may share a byte.
+  auto overlap = [&](const void* p, const void* q) {
+    const char* a = (const char*)p;
+    const char* b = (const char*)q;
+    const size_t n = sizeof(float) * (size_t)c->N;
+    return a < b + n && b < a + n;
+  };
+  if (overlap(u0, u_out)) return fail(c, WAVE_EINVAL, "u_out must not overlap u0");
+  for (int i = 0; i < 2; ++i)
+    if (overlap(u0, c->w[i]) || overlap(u_out, c->w[i]))
+      return fail(c, WAVE_EINVAL, "u0 and u_out must not overlap the context's state");
   if (nt == 0) return copy(c, u0, u_out, c->N);
   const bool untiled = c->T < 0;
   const float* src = u0;
