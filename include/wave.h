@@ -288,6 +288,25 @@ wave_status diff_init(const diff_desc* d, void* state_dev, size_t state_bytes, v
  * WAVE_ESTATE (not a diffusion context), WAVE_EUNSUPPORTED, WAVE_EHIP. */
 wave_status diff_forward(wave_ctx* ctx, int32_t nt, const float* u0_dev, float* u_out_dev);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): wave_forward
+ * without checkpoints and without a scratch argument.  Its point tables,
+ * forcing table and sample buffer live in a static device array of
+ * WAVE_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; the call allocates nothing.  The caller still
+ * passes inputs and outputs (as in wave_forward; u_init_dev / u_final_dev may
+ * be NULL).  All calls on one GPU share that GPU's array: calls that overlap
+ * in time on one GPU (any contexts, any streams) race and give wrong results.
+ * A call needing more scratch than the maximum (its size is
+ * wave_scratch_bytes(ctx, nt, nsrc, nrec, 0, 0)) returns WAVE_ENOMEM and
+ * launches nothing.  Other errors as wave_forward. */
+#define WAVE_STATIC_SCRATCH_BYTES (32u << 20)
+wave_status wave_forward_static(wave_ctx* ctx, int32_t nt,
+                                int32_t nsrc, const double* src_xyz, const float* wavelet_dev,
+                                int32_t nrec, const double* rec_xyz, float* rec_dev,
+                                const float* u_init_dev, float* u_final_dev);
+
 const char* wave_strerror(wave_status s);
 const char* wave_last_error(const wave_ctx* ctx);
 void wave_destroy(wave_ctx* ctx);

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,10 @@
 #include "wave_launch.h"
 
 using namespace wavett;
+
+// Device address of the static scratch array on the current device (resolved
+// once per device); defined at the end of this file.
+static hipError_t static_scratch_address(void** out);
 
 // =========================================================== context
 
@@ -71,6 +76,7 @@ struct wave_ctx {
   Recorder* rec = nullptr;       // non-null: device operations are recorded, not launched
   uint64_t id = 0;               // unique per context of the process
   uint64_t gen = 0;              // bumped by every call that rewrites the caller's scratch
+  void* static_scratch = nullptr;   // device address of this GPU's static scratch array (wave_forward_static)
   BatchGraph* graph = nullptr;   // last batch led by this context
   hipStream_t cap = nullptr;     // stream the batch is captured on (the caller's may be the null stream)
   std::string err;
@@ -879,6 +885,13 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
       c->max_lds = prop.sharedMemPerBlock > 0 ? prop.sharedMemPerBlock : 65536;
     }
   }
+  {
+    const hipError_t e = static_scratch_address(&c->static_scratch);
+    if (e != hipSuccess) {
+      delete c;
+      return WAVE_EHIP;
+    }
+  }
   // coefficients: FP64 then rounded once
   double cw[9];
   fd_weights(d->space_order, cw);
@@ -1623,6 +1636,62 @@ wave_status diff_forward(wave_ctx* c, int32_t nt, const float* u0, float* u_out)
     done += T;
   }
   return WAVE_OK;
+}
+
+}  // extern "C"
+
+// ====================================================== static scratch
+
+// Scratch of wave_forward_static: one array per GPU, in the code object's
+// device data, so that a call needs no allocation.  Host code never uses the
+// array's name as an address (it is a host-side stand-in there); the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current, and is kept per device.
+static __device__ __align__(256) unsigned char scratch[WAVE_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_addr[kMaxDevices] = {};
+}  // namespace
+
+static hipError_t static_scratch_address(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_static_addr[dev] = p;
+  }
+  *out = g_static_addr[dev];
+  return hipSuccess;
+}
+
+extern "C" {
+
+wave_status wave_forward_static(wave_ctx* c, int32_t nt, int32_t nsrc, const double* src, const float* wav,
+                                int32_t nrec, const double* rec, float* rec_out, const float* u_init,
+                                float* u_final) {
+  if (!c) return WAVE_EINVAL;
+  c->err.clear();
+  if (c->eq != 0) return fail(c, WAVE_ESTATE, "not a wave-equation context");
+  if (!c->static_scratch) return fail(c, WAVE_EHIP, "static scratch address not resolved");
+  if (nt < 0 || nsrc < 0 || nrec < 0) return fail(c, WAVE_EINVAL, "negative nt or point count");
+  const size_t need = layout(c, nt, nsrc, nrec, 0, 0).total;
+  if (need > (size_t)WAVE_STATIC_SCRATCH_BYTES) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "call needs %zu bytes of scratch, above the static maximum of %zu",
+                  need, (size_t)WAVE_STATIC_SCRATCH_BYTES);
+    return fail(c, WAVE_ENOMEM, buf);
+  }
+  return wave_forward(c, nt, nsrc, src, wav, nrec, rec, rec_out, u_init, u_final, 0, c->static_scratch,
+                      (size_t)WAVE_STATIC_SCRATCH_BYTES);
 }
 
 }  // extern "C"

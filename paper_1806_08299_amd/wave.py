@@ -109,6 +109,7 @@ def lib():
             "wave_get_schedule": (i32, [P, P, P, P, P]),
             "wave_scratch_bytes": (sz, [P, i32, i32, i32, i32, i32]),
             "wave_forward": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, P, sz]),
+            "wave_forward_static": (i32, [P, i32, i32, P, P, i32, P, P, P, P]),
             "wave_adjoint_grad": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, i32, P, sz]),
             "wave_batch": (i32, [P, i32, i32, P, P, P, P, P, P, P, P, i32, P, P]),
             "wave_autotune": (i32, [P, i32, i32, i32, P, sz, P]),
@@ -209,6 +210,19 @@ def wave_forward(ctx, nt, src_xyz, wavelet, rec_xyz, rec_out, u_init, u_final, c
                             _dptr(rec_out), _dptr(u_init), _dptr(u_final), ckpt_every,
                             ctypes.c_void_p(scratch.data_ptr()), scratch.numel() * scratch.element_size())
     _check(st, ctx)
+
+
+def wave_forward_static(ctx, nt, src_xyz, wavelet, rec_xyz, rec_out, u_init, u_final, ndim):
+    """wave_forward without checkpoints or a scratch argument: the library's
+    static per-GPU scratch array is used (for callers that cannot allocate)."""
+    src = _coords(src_xyz, ndim)
+    rec = _coords(rec_xyz, ndim)
+    st = lib().wave_forward_static(ctx, nt, src.shape[0], _hptr(src), _dptr(wavelet), rec.shape[0], _hptr(rec),
+                                   _dptr(rec_out), _dptr(u_init), _dptr(u_final))
+    _check(st, ctx)
+
+
+WAVE_STATIC_SCRATCH_BYTES = 32 << 20
 
 
 def wave_adjoint_grad(ctx, nt, src_xyz, wavelet, rec_xyz, resid, grad_m, grad_wavelet, ckpt_every, reuse,
