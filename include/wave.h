@@ -69,17 +69,33 @@ typedef struct wave_desc {
   double dt;             /* seconds */
   int32_t nbl;           /* absorbing-layer width in points; 0 = no damping */
   double sigma_max;      /* damping maximum in 1/s (ignored if nbl == 0) */
-  int32_t time_tile;     /* T >= 1 fused steps per launch; -1 = untiled single-step
+  int32_t time_tile;     /* T >= 1 time steps per time tile; -1 = untiled single-step
                             sweep (the reference schedule); 0 = default: 3D T = 3 on
                             32x64 tiles at radius 1; 2D T = 4 up to radius 2, T = 2 up
                             to radius 4; untiled otherwise (the measured best on
                             MI355X; wave_autotune refines by timing) */
-  int32_t skew;          /* halo per fused step on the tiled axes; 0 = r; must be >= r */
-  int32_t tile_shape;    /* 3D tiled sweep: 0 = auto; 1 = 64x64 extended tile;
-                            2 = 32x64 extended tile (both 512 threads).  2D: ignored */
-  int32_t zchunks;       /* segments of axis 0 per launch; 0 = auto (untiled 3D: about
-                            32 workgroups per CU, segments of at least max(16, 4r) planes;
-                            time-tiled 2D: about 16 per CU) */
+  int32_t skew;          /* skewing factor: halo per fused step on the tiled axes (slab = 0)
+                            or plane shift per step of the skewed schedule (slab > 0);
+                            0 = r; must be >= r (background chapter, "Validity of skewing
+                            factors") */
+  int32_t tile[2];       /* register-tiled sweep (slab = 0, T >= 1): the extended tile
+                            (b1 rows along axis 1, b2 columns along the unit-stride axis)
+                            loaded by one workgroup, of which the inner (b1 - 2 skew T) x
+                            (b2 - 2 skew T) are written (Devito chapter, "Parameterisation":
+                            tile sizes as run-time parameters).  {0, 0} = auto.  Must be an
+                            entry of the table of built tiles (wave_tile_extent): 3D 64x64,
+                            32x64, 32x128, 16x128; 2D 1x1024.  Others: WAVE_EUNSUPPORTED */
+  int32_t slab;          /* > 0 (with T >= 1): the skewed schedule of the implementation
+                            chapter ("Time-tiling"): each time tile advances the grid slab by
+                            slab along axis 0, every slab all T steps (one single-step launch
+                            each, its planes shifted by -skew per step) before the next, so
+                            no point is computed twice and a slab's levels stay in the
+                            last-level cache between its steps.  The value is the slab
+                            thickness in planes (any; the tile size along axis 0).
+                            0 = register-tiled or untiled sweep */
+  int32_t zchunks;       /* segments of axis 0 per launch (of a slab, with slab > 0);
+                            0 = auto (untiled 3D: about 32 workgroups per CU, segments of
+                            at least max(16, 4r) planes; time-tiled 2D: about 16 per CU) */
 } wave_desc;
 
 typedef struct wave_ctx wave_ctx;
@@ -101,14 +117,20 @@ wave_status wave_init(const wave_desc* d, const float* m_dev, void* state_dev, s
  * NaN included). */
 wave_status wave_set_model(wave_ctx* ctx, const float* m_dev);
 
-/* Change the schedule of an existing context: T >= 1 or -1 (untiled), skew
- * (0 = r), tile_shape, zchunks as in wave_desc.  Host-only. */
-wave_status wave_set_schedule(wave_ctx* ctx, int32_t time_tile, int32_t skew, int32_t tile_shape,
-                              int32_t zchunks);
+/* Change the schedule of an existing context (the paper's run-time time-tile
+ * size, skewing factor and tile sizes; Devito chapter, "Parameterisation"):
+ * T >= 1 or -1 (untiled), skew (0 = r), tile [2] (NULL or {0, 0} = auto),
+ * slab and zchunks as in wave_desc.  Host-only.  Errors: WAVE_EINVAL,
+ * WAVE_ESKEW, WAVE_EUNSUPPORTED (tile not built, depth above the tile's
+ * limit, no core left); the schedule is then unchanged. */
+wave_status wave_set_schedule(wave_ctx* ctx, int32_t time_tile, int32_t skew, const int32_t* tile,
+                              int32_t slab, int32_t zchunks);
 
-/* Read back the schedule in use (after autotuning). Any pointer may be NULL. */
-wave_status wave_get_schedule(const wave_ctx* ctx, int32_t* time_tile, int32_t* skew, int32_t* tile_shape,
-                              int32_t* zchunks);
+/* Read back the schedule in use (after autotuning): tile receives the
+ * extended tile {b1, b2} of the register-tiled sweep ({0, 0} when the
+ * schedule is untiled or skewed).  Any pointer may be NULL. */
+wave_status wave_get_schedule(const wave_ctx* ctx, int32_t* time_tile, int32_t* skew, int32_t* tile,
+                              int32_t* slab, int32_t* zchunks);
 
 /* Scratch bytes needed by wave_forward (adjoint = 0), by wave_forward with
  * checkpoints followed by wave_adjoint_grad (adjoint = 1), or by one shot of
@@ -217,16 +239,20 @@ double wave_ai_naive(double ai_space, int32_t t_t);
 double wave_ai_tight(double ai_space, int32_t t_t, int32_t ndim, const double* D, const double* delta,
                      const double* tile, double omega);
 
-/* Largest fused depth T built for this order, dimension and tile shape
- * (3D: tile_shape 1 or 2; 2D: ignored); 0 if none.  Bounded by the register
- * file: every fused level keeps a (so+1)-plane window per column.  Host-only. */
-int32_t wave_tiled_max_depth(int32_t space_order, int32_t ndim, int32_t tile_shape);
+/* Largest fused depth T of the register-tiled sweep built for this order,
+ * dimension and extended tile {ey, ex} (an entry of wave_tile_extent's
+ * table); 0 if none.  Bounded by the register file (every fused level keeps
+ * a (so+1)-plane window per column) and by the core (ey - 2 r T >= 1).  The
+ * skewed schedule (slab > 0) has no such bound.  Host-only. */
+int32_t wave_tiled_max_depth(int32_t space_order, int32_t ndim, int32_t ey, int32_t ex);
 
-/* Extended (y, x) tile of one workgroup of the time-tiled sweep for
- * tile_shape (ignored in 2D, where y is 1): the columns it loads, of which
- * the inner (ey - 2 skew T) x (ex - 2 skew T) are written.  Host-only.
- * Returns WAVE_EINVAL for an unknown shape or ndim. */
-wave_status wave_tile_extent(int32_t ndim, int32_t tile_shape, int32_t* ey, int32_t* ex);
+/* Entry `index` (1, 2, ...) of the table of extended tiles built for the
+ * register-tiled sweep in ndim dimensions (Devito chapter, "Parameterisation";
+ * the run-time tile sizes are drawn from it): the rows ey along axis 1 and
+ * columns ex along the unit-stride axis that one workgroup loads.  3D: 1 =
+ * 64x64, 2 = 32x64, 3 = 32x128, 4 = 16x128; 2D: 1 = 1x1024.  Host-only.
+ * Returns WAVE_EINVAL past the end of the table or for a bad ndim. */
+wave_status wave_tile_extent(int32_t ndim, int32_t index, int32_t* ey, int32_t* ex);
 
 /* Flops per point-update of the sweep (adds + multiplies, FMA = 2) for order
  * so in ndim dimensions, and compulsory HBM bytes per point-update of the
@@ -262,7 +288,8 @@ typedef struct diff_desc {
                             up to radius 4; untiled otherwise -- the measured best on
                             MI355X) */
   int32_t skew;          /* 0 = r; must be >= r */
-  int32_t tile_shape;    /* as in wave_desc */
+  int32_t tile[2];       /* as in wave_desc */
+  int32_t slab;          /* as in wave_desc */
   int32_t zchunks;       /* as in wave_desc; 0 = auto (time-tiled: about 6 workgroups per CU
                             in 3D, 16 in 2D) */
 } diff_desc;

@@ -60,7 +60,9 @@ struct wave_ctx {
   float* w[4] = {nullptr, nullptr, nullptr, nullptr};
   hipStream_t stream = nullptr;
   // schedule: T == -1 untiled kernel, T >= 1 tiled kernel
-  int T = -1, skew = 0, shape = 1, zchunks = 0;
+  // shape: index into the table of extended tiles of the register-tiled
+  // sweep (3D 1..kNumShapes3D; 2D 0); slab > 0: skewed schedule (T >= 1)
+  int T = -1, skew = 0, shape = 1, zchunks = 0, slab = 0;
   int num_cu = 256;
   size_t max_lds = 65536;
   // checkpoints left by the last forward (for reuse by the adjoint)
@@ -134,6 +136,22 @@ int64_t npts_of(const wave_desc* d) {
   return n;
 }
 
+// Table index of the extended tile {ey, ex} of the register-tiled sweep:
+// 3D 1..kNumShapes3D, 2D 0 (its one tile); {0, 0} = 0 (automatic); -1 if
+// the tile is not built.
+int tile_index(int ndim, int ey, int ex) {
+  if (ey == 0 && ex == 0) return 0;
+  if (ndim == 2) {
+    const BlockShape bs = block_shape(KIND_TILED, 2, 0);
+    return (ey == bs.ey && ex == bs.ex) ? 0 : -1;
+  }
+  for (int i = 1; i <= kNumShapes3D; ++i) {
+    const BlockShape bs = block_shape(KIND_TILED, 3, i);
+    if (ey == bs.ey && ex == bs.ex) return i;
+  }
+  return -1;
+}
+
 wave_status check_desc(const wave_desc* d, std::string& msg) {
   if (!d) { msg = "null descriptor"; return WAVE_EINVAL; }
   if (d->ndim != 2 && d->ndim != 3) { msg = "ndim must be 2 or 3"; return WAVE_EINVAL; }
@@ -158,7 +176,12 @@ wave_status check_desc(const wave_desc* d, std::string& msg) {
   if (d->skew != 0 && d->skew < r) { msg = "skew below the stencil radius"; return WAVE_ESKEW; }
   if (d->skew < 0) { msg = "bad skew"; return WAVE_EINVAL; }
   if (d->time_tile < -1 || d->time_tile > 8) { msg = "time_tile must be -1, 0 or 1..8"; return WAVE_EINVAL; }
-  if (d->tile_shape < 0 || d->tile_shape > 2) { msg = "tile_shape must be 0, 1 or 2"; return WAVE_EINVAL; }
+  if (d->tile[0] < 0 || d->tile[1] < 0) { msg = "negative tile extent"; return WAVE_EINVAL; }
+  if (tile_index(d->ndim, d->tile[0], d->tile[1]) < 0) {
+    msg = "tile extent not in the table of built tiles";
+    return WAVE_EUNSUPPORTED;
+  }
+  if (d->slab < 0) { msg = "slab must be >= 0"; return WAVE_EINVAL; }
   if (d->zchunks < 0) { msg = "zchunks must be >= 0"; return WAVE_EINVAL; }
   return WAVE_OK;
 }
@@ -370,6 +393,7 @@ wave_status copy(wave_ctx* c, const float* s, float* d, int64_t n) {
 struct Plan {
   int kind, T, shape;
   int tiles_x, tiles_y, zchunk, zc;
+  int zlo, zhi;   // planes the launch updates
   size_t lds;
   int core_y, core_x;
 };
@@ -379,7 +403,7 @@ struct Plan {
 // 298-299 Gpts/s, 12 segments 285), i.e. about 32 workgroups per CU; the
 // time-tiled sweeps want very different counts by depth and order, which
 // wave_autotune finds.
-int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T) {
+int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T, int64_t nz) {
   // time-tiled diffusion (one level per stage, fewer registers): ~6 per CU
   // (500^3, order 2, depth 4: 8 segments 1481 Gpts/s, 3 segments 1111).
   // 2D (a row of 1 x 1024 tiles per plane): ~16 per CU (16384^2 wave,
@@ -390,11 +414,16 @@ int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T) {
   // A segment re-reads 2R planes of window fill: keep it at least 4R long.
   const int64_t min_len = (kind == KIND_UNTILED) ? std::max<int64_t>(16, 4LL * c->R)
                                                  : std::max<int64_t>(16, 4LL * T * c->R);
-  zc = std::min<int64_t>(zc, std::max<int64_t>(1, c->n0 / min_len));
+  zc = std::min<int64_t>(zc, std::max<int64_t>(1, nz / min_len));
   return (int)std::max<int64_t>(1, zc);
 }
 
-wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p) {
+// Plan of one launch over planes [zlo, zhi) (zhi < 0: the whole grid).
+wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p, int64_t zlo = 0, int64_t zhi = -1) {
+  if (zhi < 0) zhi = c->n0;
+  p.zlo = (int)zlo;
+  p.zhi = (int)zhi;
+  const int64_t nz = zhi - zlo;
   p.kind = kind;
   p.T = T;
   p.shape = (c->dim == 3) ? c->shape : 0;
@@ -418,9 +447,9 @@ wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p) {
   p.tiles_x = (int)((c->n2 + p.core_x - 1) / p.core_x);
   p.tiles_y = (int)((ny + p.core_y - 1) / p.core_y);
   const int64_t base = (int64_t)p.tiles_x * p.tiles_y;
-  int zc = c->zchunks > 0 ? c->zchunks : auto_zchunks(c, base, kind, T);
-  zc = (int)std::min<int64_t>(zc, c->n0);
-  p.zchunk = (int)((c->n0 + zc - 1) / zc);
+  int zc = c->zchunks > 0 ? c->zchunks : auto_zchunks(c, base, kind, T, nz);
+  zc = (int)std::min<int64_t>(zc, nz);
+  p.zchunk = (int)((nz + zc - 1) / zc);
   // A workgroup addresses its segment of planes (chunk plus pipeline halo)
   // through one buffer descriptor per array, at most kSegMax bytes.
   const int64_t plane_bytes = c->n1 * c->n2 * (int64_t)sizeof(float);
@@ -428,7 +457,7 @@ wave_status make_plan(wave_ctx* c, int kind, int T, Plan& p) {
   const int64_t max_chunk = (int64_t)kSegMax / plane_bytes - halo;
   if (max_chunk < 1) return fail(c, WAVE_EUNSUPPORTED, "grid plane too large for one buffer segment");
   if (p.zchunk > max_chunk) p.zchunk = (int)max_chunk;
-  p.zc = (int)((c->n0 + p.zchunk - 1) / p.zchunk);
+  p.zc = (int)((nz + p.zchunk - 1) / p.zchunk);
   return WAVE_OK;
 }
 
@@ -458,6 +487,8 @@ wave_status launch_window(wave_ctx* c, const Plan& p, SweepArgs A) {
   A.ntiles = p.tiles_x * p.tiles_y;
   A.nblocks = A.ntiles * p.zc;
   A.zchunk = p.zchunk;
+  A.zlo = p.zlo;
+  A.zhi = p.zhi;
   dim3 grid((unsigned)A.nblocks);
   int mode = MODE_FWD;
   if (c->eq == 1) mode = MODE_DIFF;
@@ -490,9 +521,7 @@ struct Waves {
   float* P() const { return buf[prev]; }
 };
 
-// Advance `steps` steps starting at step index `step0` (direction dir), using
-// windows of the context's depth.  Stops windows at multiples of `cut`
-// (relative to cut_origin) when cut > 0.
+// The tables and outputs a run of steps hands to every launch.
 struct Window {
   const DevPoints* inj;
   const float* inj_table;
@@ -504,7 +533,77 @@ struct Window {
   const SweepAux* aux;   // device copy of the forcing/sampling tables
 };
 
+// Launch arguments common to every launch of a run: forcing and sampling
+// tables, history and gradient.
+SweepArgs window_args(const wave_ctx* c, const Window& win) {
+  SweepArgs A = base_args(c);
+  A.aux = win.aux;
+  if (win.inj && win.inj->set.npts > 0) {
+    A.inj_zlo = win.inj->zlo;
+    A.inj_zhi = win.inj->zhi;
+  }
+  if (win.smp && win.smp->set.npts > 0 && win.smp_out) {
+    A.smp_zlo = win.smp->zlo;
+    A.smp_zhi = win.smp->zhi;
+  }
+  A.hist = win.hist;
+  A.hist_base = win.hist_base;
+  A.grad = win.grad;
+  return A;
+}
+
+// The skewed schedule (slab Z > 0, skew s >= r, depth T): the paper's time
+// tile with the spatial loop along axis 0 skewed by the time index
+// (implementation chapter, "Time-tiling"; background chapter, "Skewing"),
+// executed tile after tile in their dependence order.  Step k of a time tile
+// (0 <= k < T) updates, for slab j, the planes [jZ - ks, (j+1)Z - ks) clipped
+// to the grid, and slab j runs all T steps before slab j+1.  Every plane of
+// every step is computed exactly once, by the single-step kernel, so the
+// result is bitwise that of the untiled sweep.  Legality with the two
+// in-place levels (level n+1 overwrites n-1): the z-stencil of step k reads
+// level n on [jZ-ks-r, (j+1)Z-ks+r); its right part lies in slab j's step k-1
+// (s >= r), its left part in earlier slabs, and no later write has reached it
+// yet, since step k+1 of slab j-1 stopped at jZ-(k+1)s <= jZ-ks-r.  Level n-1
+// is read at the point only, which the in-place update reads before writing.
+// Slab j's steps touch about Z + T s + 2r planes, which stay in the
+// last-level cache between its launches.
+wave_status run_steps_skewed(wave_ctx* c, Waves& W, int step0, int steps, int dir, const Window& win) {
+  const int64_t s = c->skew, Z = c->slab;
+  int done = 0;
+  while (done < steps) {
+    const int Tw = std::min(c->T, steps - done);
+    const int64_t J = (c->n0 + (int64_t)(Tw - 1) * s + Z - 1) / Z;
+    for (int64_t j = 0; j < J; ++j) {
+      for (int k = 0; k < Tw; ++k) {
+        const int64_t lo = std::max<int64_t>(0, j * Z - k * s);
+        const int64_t hi = std::min<int64_t>(c->n0, (j + 1) * Z - k * s);
+        if (lo >= hi) continue;
+        Plan p;
+        wave_status st = make_plan(c, KIND_UNTILED, 1, p, lo, hi);
+        if (st != WAVE_OK) return st;
+        SweepArgs A = window_args(c, win);
+        // level done+k sits in C() for even k, in P() for odd k
+        float* cur = (k & 1) ? W.P() : W.C();
+        float* old = (k & 1) ? W.C() : W.P();
+        A.cur = cur;
+        A.prev = old;
+        A.outA = old;   // in place over the oldest level
+        A.outB = nullptr;
+        A.step0 = step0 + dir * (done + k);
+        A.dir = dir;
+        if ((st = launch_window(c, p, A)) != WAVE_OK) return st;
+      }
+    }
+    if (Tw & 1) std::swap(W.cur, W.prev);
+    done += Tw;
+  }
+  return WAVE_OK;
+}
+
+// Advance `steps` steps starting at step index `step0` (direction dir), in
+// windows of the context's depth.
 wave_status run_steps(wave_ctx* c, Waves& W, int step0, int steps, int dir, const Window& win) {
+  if (c->T >= 1 && c->slab > 0) return run_steps_skewed(c, W, step0, steps, dir, win);
   int done = 0;
   const bool untiled = (c->T < 0);
   while (done < steps) {
@@ -512,21 +611,9 @@ wave_status run_steps(wave_ctx* c, Waves& W, int step0, int steps, int dir, cons
     Plan p;
     wave_status s = make_plan(c, untiled ? KIND_UNTILED : KIND_TILED, T, p);
     if (s != WAVE_OK) return s;
-    SweepArgs A = base_args(c);
+    SweepArgs A = window_args(c, win);
     A.cur = W.C();
     A.prev = W.P();
-    A.aux = win.aux;
-    if (win.inj && win.inj->set.npts > 0) {
-      A.inj_zlo = win.inj->zlo;
-      A.inj_zhi = win.inj->zhi;
-    }
-    if (win.smp && win.smp->set.npts > 0 && win.smp_out) {
-      A.smp_zlo = win.smp->zlo;
-      A.smp_zhi = win.smp->zhi;
-    }
-    A.hist = win.hist;
-    A.hist_base = win.hist_base;
-    A.grad = win.grad;
     A.step0 = step0 + dir * done;
     A.dir = dir;
     int nc, np;
@@ -687,13 +774,20 @@ BlockShape block_shape(int kind, int dim, int shape) {
   if (dim == 2) return {4, 4, 1, 1024};
   if (kind == KIND_UNTILED) return {WAVE_UNTILED_NW, WAVE_UNTILED_RY, WAVE_UNTILED_NW * WAVE_UNTILED_RY, 64};
   if (shape == 2) return {8, 4, 32, 64};
+  if (shape == 3) return {16, 4, 32, 128};
+  if (shape == 4) return {8, 4, 16, 128};
   return {8, 8, 64, 64};
 }
 
 int tiled_tmax(int R, int dim, int shape) {
   if (R < 1 || R > 8) return 0;
   if (dim == 2) return kTmax2D[R];
-  return shape == 2 ? kTmax3D_S2[R] : kTmax3D_S1[R];
+  switch (shape) {
+    case 2: return kTmax3D_S2[R];
+    case 3: return kTmax3D_S3[R];
+    case 4: return kTmax3D_S4[R];
+    default: return kTmax3D_S1[R];
+  }
 }
 
 hipError_t launch_sweep(int R, int kind, int T, int dim, int mode, int shape, const SweepArgs& A, dim3 grid,
@@ -759,15 +853,18 @@ size_t wave_state_bytes(const wave_desc* d) {
   return o;
 }
 
-static wave_status apply_schedule(wave_ctx* c, int T, int skew, int shape, int zchunks) {
+static wave_status apply_schedule(wave_ctx* c, int T, int skew, int shape, int slab, int zchunks) {
   if (skew != 0 && skew < c->R) return fail(c, WAVE_ESKEW, "skew below the stencil radius");
-  if (skew < 0 || zchunks < 0 || shape < 0 || shape > 2 || T < -1 || T > 8 || T == 0)
+  if (skew < 0 || zchunks < 0 || slab < 0 || shape < 0 || shape > kNumShapes3D || T < -1 || T == 0)
     return fail(c, WAVE_EINVAL, "bad schedule");
+  if (slab == 0 && T > 8) return fail(c, WAVE_EUNSUPPORTED, "register-tiled depth above 8");
+  if (slab > 0 && T < 1) return fail(c, WAVE_EINVAL, "the skewed schedule needs a depth T >= 1");
   c->T = T;
   c->skew = skew ? skew : c->R;
   c->shape = (c->dim == 3) ? (shape ? shape : 1) : 0;
+  c->slab = slab;
   c->zchunks = zchunks;
-  if (T >= 1) {
+  if (T >= 1 && slab == 0) {
     Plan p;
     wave_status s = make_plan(c, KIND_TILED, T, p);
     if (s != WAVE_OK) return s;
@@ -775,21 +872,35 @@ static wave_status apply_schedule(wave_ctx* c, int T, int skew, int shape, int z
   return WAVE_OK;
 }
 
-wave_status wave_set_schedule(wave_ctx* c, int32_t T, int32_t skew, int32_t shape, int32_t zchunks) {
+wave_status wave_set_schedule(wave_ctx* c, int32_t T, int32_t skew, const int32_t* tile, int32_t slab,
+                              int32_t zchunks) {
   if (!c) return WAVE_EINVAL;
-  const int oT = c->T, os = c->skew, osh = c->shape, oz = c->zchunks;
-  wave_status s = apply_schedule(c, T, skew, shape, zchunks);
+  const int ey = tile ? tile[0] : 0, ex = tile ? tile[1] : 0;
+  if (ey < 0 || ex < 0) return fail(c, WAVE_EINVAL, "negative tile extent");
+  const int shape = tile_index(c->dim, ey, ex);
+  if (shape < 0) return fail(c, WAVE_EUNSUPPORTED, "tile extent not in the table of built tiles");
+  const int oT = c->T, os = c->skew, osh = c->shape, oz = c->zchunks, osl = c->slab;
+  wave_status s = apply_schedule(c, T, skew, shape, slab, zchunks);
   if (s != WAVE_OK) {
-    c->T = oT; c->skew = os; c->shape = osh; c->zchunks = oz;
+    c->T = oT; c->skew = os; c->shape = osh; c->zchunks = oz; c->slab = osl;
   }
   return s;
 }
 
-wave_status wave_get_schedule(const wave_ctx* c, int32_t* T, int32_t* skew, int32_t* shape, int32_t* zchunks) {
+wave_status wave_get_schedule(const wave_ctx* c, int32_t* T, int32_t* skew, int32_t* tile, int32_t* slab,
+                              int32_t* zchunks) {
   if (!c) return WAVE_EINVAL;
   if (T) *T = c->T;
   if (skew) *skew = c->skew;
-  if (shape) *shape = c->shape;
+  if (tile) {
+    tile[0] = tile[1] = 0;
+    if (c->T >= 1 && c->slab == 0) {
+      const BlockShape bs = block_shape(KIND_TILED, c->dim, c->shape);
+      tile[0] = bs.ey;
+      tile[1] = bs.ex;
+    }
+  }
+  if (slab) *slab = c->slab;
   if (zchunks) *zchunks = c->zchunks;
   return WAVE_OK;
 }
@@ -914,7 +1025,8 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
     p += align_up(sizeof(float) * c->N);
   }
   const int T0 = d->time_tile == 0 ? -2 : d->time_tile;
-  s = apply_schedule(c, T0 == -2 ? -1 : T0, d->skew, d->tile_shape, d->zchunks);
+  const int shape0 = tile_index(d->ndim, d->tile[0], d->tile[1]);
+  s = apply_schedule(c, T0 == -2 ? -1 : T0, d->skew, shape0, T0 == -2 ? 0 : d->slab, d->zchunks);
   if (s != WAVE_OK) {
     delete c;
     return s;
@@ -936,7 +1048,7 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
     const int Td = c->dim == 3 ? (c->R <= 1 ? 3 : 0) : (c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0));
     if (Td > 0) {
       const int oshape = c->shape;
-      if (c->dim == 3 && d->tile_shape == 0) c->shape = 2;
+      if (c->dim == 3 && shape0 == 0) c->shape = 2;
       Plan pl;
       if (make_plan(c, KIND_TILED, Td, pl) == WAVE_OK) best = Td;
       else c->shape = oshape;
@@ -1202,7 +1314,10 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const 
     for (int j = 0; j < i; ++j)
       if (ctxs[j] == c) return fail(lead, WAVE_EINVAL, "a context appears twice in the batch");
     if (c->stream != st) return fail(lead, WAVE_EINVAL, "all contexts of a batch must share one stream");
-    if (c->T > kBatchTmax) return fail(lead, WAVE_EUNSUPPORTED, "batched shots need the untiled sweep or depth <= 2");
+    if (c->T >= 1 && c->slab == 0 && (c->T > kBatchTmax || (c->dim == 3 && c->shape > 2)))
+      return fail(lead, WAVE_EUNSUPPORTED,
+                  "batched shots need the untiled sweep, the skewed schedule or a register-tiled depth <= 2 "
+                  "on a 64x64 or 32x64 tile");
     wave_status s;
     if ((s = validate_coords(c, nsrc[i], src_xyz[i])) || (s = validate_coords(c, nrec[i], rec_xyz[i])))
       return fail(lead, s, "shot " + std::to_string(i) + ": " + c->err);
@@ -1220,7 +1335,7 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const 
     std::vector<uint64_t> sig = {(uint64_t)nshots, (uint64_t)nt, (uint64_t)Kf, (uint64_t)grad};
     for (int i = 0; i < nshots; ++i) {
       const wave_ctx* c = ctxs[i];
-      const uint64_t v[] = {c->id, c->gen, (uint64_t)c->T, (uint64_t)c->skew, (uint64_t)c->shape,
+      const uint64_t v[] = {c->id, c->gen, (uint64_t)c->T, (uint64_t)c->skew, (uint64_t)c->shape, (uint64_t)c->slab,
                           (uint64_t)c->zchunks, (uint64_t)nsrc[i], (uint64_t)nrec[i],
                           (uint64_t)(uintptr_t)wavelet_dev[i], (uint64_t)(uintptr_t)rec_dev[i],
                           (uint64_t)(uintptr_t)(grad ? dobs_dev[i] : nullptr),
@@ -1338,21 +1453,27 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
     wave_status fs = fill(c, (float*)scratch, c->N, 0.0f);
     if (fs != WAVE_OK) return fs;
   }
-  struct Cand { int T, skew, shape, zc; };
+  struct Cand { int T, skew, shape, slab, zc; };
   std::vector<Cand> cands;
-  cands.push_back({-1, c->R, c->shape ? c->shape : 1, 0});
-  const int shapes[2] = {1, 2};
-  for (int si = 0; si < (c->dim == 3 ? 2 : 1); ++si) {
-    const int sh = c->dim == 3 ? shapes[si] : 0;
-    const int tm = std::min<int>(max_T > 0 ? max_T : 8, tiled_tmax(c->R, c->dim, sh ? sh : 0));
-    for (int T = 1; T <= tm; ++T) cands.push_back({T, c->R, sh, 0});
+  cands.push_back({-1, c->R, c->shape ? c->shape : 1, 0, 0});
+  // register-tiled: every built tile and depth at the minimum skew
+  const int nshapes = c->dim == 3 ? kNumShapes3D : 1;
+  for (int si = 1; si <= nshapes; ++si) {
+    const int sh = c->dim == 3 ? si : 0;
+    const int tm = std::min<int>(max_T > 0 ? max_T : 8, tiled_tmax(c->R, c->dim, sh));
+    for (int T = 1; T <= tm; ++T) cands.push_back({T, c->R, sh, 0, 0});
   }
-  const int oT = c->T, os = c->skew, osh = c->shape, oz = c->zchunks;
+  // skewed: depths 2..16 (up to max_T) on slabs of 32 and 64 planes
+  const int tskew = max_T > 0 ? max_T : 16;
+  for (int T = 2; T <= tskew && T <= trial_steps; T *= 2)
+    for (int Z : {32, 64})
+      if (Z < c->n0) cands.push_back({T, c->R, c->shape ? c->shape : 1, Z, 0});
+  const int oT = c->T, os = c->skew, osh = c->shape, oz = c->zchunks, osl = c->slab;
   hipEvent_t e0, e1;
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
   auto time_one = [&](const Cand& k) -> double {
-    if (apply_schedule(c, k.T, k.skew, k.shape ? k.shape : 1, k.zc) != WAVE_OK) return 1e300;
+    if (apply_schedule(c, k.T, k.skew, k.shape ? k.shape : 1, k.slab, k.zc) != WAVE_OK) return 1e300;
     double tmin = 1e300;
     for (int r = 0; r < repeats + 1; ++r) {
       hipEventRecord(e0, c->stream);
@@ -1369,13 +1490,20 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
     }
     return tmin;
   };
-  // Phase 1: depth and tile shape at the default number of axis-0 segments.
+  auto better = [](const std::pair<double, Cand>& x, const std::pair<double, Cand>& y) { return x.first < y.first; };
+  // Phase 1: kind, depth and tile at the default number of axis-0 segments.
   std::vector<std::pair<double, Cand>> timed;
   for (const Cand& k : cands) timed.push_back({time_one(k), k});
-  std::stable_sort(timed.begin(), timed.end(),
-                   [](const std::pair<double, Cand>& x, const std::pair<double, Cand>& y) { return x.first < y.first; });
+  std::stable_sort(timed.begin(), timed.end(), better);
   double best_t = timed.empty() ? 1e300 : timed[0].first;
-  Cand bc = timed.empty() ? Cand{oT, os, osh, oz} : timed[0].second;
+  Cand bc = timed.empty() ? Cand{oT, os, osh, osl, oz} : timed[0].second;
+  auto consider = [&](const Cand& k) {
+    const double t = time_one(k);
+    if (t < best_t) {
+      best_t = t;
+      bc = k;
+    }
+  };
   // Phase 2: the number of axis-0 segments (grid size against per-workgroup
   // pipeline fill) for the five fastest schedules: at low orders a time-tiled
   // schedule that phase 1 ranks behind the untiled sweep can overtake it
@@ -1387,19 +1515,42 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
       if (z > c->n0) break;
       Cand k = timed[t].second;
       k.zc = z;
-      const double tz = time_one(k);
-      if (tz < best_t) {
-        best_t = tz;
-        bc = k;
-      }
+      consider(k);
+    }
+  }
+  // Phase 3: the skewing factor of the best register-tiled schedule (the
+  // minimum legal skew r, a multiple of four, twice r), or the slab
+  // thickness and depth of the best skewed schedule.
+  if (bc.T >= 1 && bc.slab == 0) {
+    const Cand b0 = bc;
+    for (int sk : {(c->R + 3) / 4 * 4, 2 * c->R}) {
+      if (sk == b0.skew) continue;
+      Cand k = b0;
+      k.skew = sk;
+      consider(k);
+    }
+  } else if (bc.slab > 0) {
+    const Cand b0 = bc;
+    for (int Z : {16, 24, 48, 96, 128}) {
+      if (Z >= c->n0) continue;
+      Cand k = b0;
+      k.slab = Z;
+      consider(k);
+    }
+    const Cand b1 = bc;
+    for (int T : {b1.T / 2, b1.T * 2}) {
+      if (T < 2 || T > trial_steps || T > tskew) continue;
+      Cand k = b1;
+      k.T = T;
+      consider(k);
     }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->err.clear();
-  wave_status s = apply_schedule(c, bc.T, bc.skew, bc.shape ? bc.shape : 1, bc.zc);
+  wave_status s = apply_schedule(c, bc.T, bc.skew, bc.shape ? bc.shape : 1, bc.slab, bc.zc);
   if (s != WAVE_OK) {
-    c->T = oT; c->skew = os; c->shape = osh; c->zchunks = oz;
+    c->T = oT; c->skew = os; c->shape = osh; c->zchunks = oz; c->slab = osl;
     return s;
   }
   if (best) *best = best_t / trial_steps;
@@ -1408,10 +1559,11 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
 
 // ----------------------------------------------------------- estimators
 
-int32_t wave_tiled_max_depth(int32_t space_order, int32_t ndim, int32_t tile_shape) {
+int32_t wave_tiled_max_depth(int32_t space_order, int32_t ndim, int32_t ey, int32_t ex) {
   if (space_order < 2 || space_order > 16 || (space_order & 1) || (ndim != 2 && ndim != 3)) return 0;
-  if (ndim == 3 && tile_shape != 1 && tile_shape != 2) return 0;
-  return tiled_tmax(space_order / 2, ndim, ndim == 3 ? tile_shape : 0);
+  const int shape = tile_index(ndim, ey, ex);
+  if (shape < 0 || (ndim == 3 && shape == 0)) return 0;
+  return tiled_tmax(space_order / 2, ndim, shape);
 }
 
 double wave_ai_naive(double ai_space, int32_t t_t) { return ai_space * (double)t_t; }
@@ -1442,10 +1594,10 @@ double wave_ai_tight(double ai_space, int32_t t_t, int32_t n, const double* D, c
   return wave_ai_naive(ai_space, t_t) / (1.0 + frac);
 }
 
-wave_status wave_tile_extent(int32_t ndim, int32_t tile_shape, int32_t* ey, int32_t* ex) {
-  if ((ndim != 2 && ndim != 3) || (ndim == 3 && (tile_shape < 0 || tile_shape > 2)) || !ey || !ex)
-    return WAVE_EINVAL;
-  const BlockShape bs = block_shape(KIND_TILED, ndim, tile_shape == 0 ? 1 : tile_shape);
+wave_status wave_tile_extent(int32_t ndim, int32_t index, int32_t* ey, int32_t* ex) {
+  if ((ndim != 2 && ndim != 3) || !ey || !ex) return WAVE_EINVAL;
+  if (index < 1 || index > (ndim == 3 ? kNumShapes3D : 1)) return WAVE_EINVAL;
+  const BlockShape bs = block_shape(KIND_TILED, ndim, ndim == 3 ? index : 0);
   *ey = bs.ey;
   *ex = bs.ex;
   return WAVE_OK;
@@ -1496,7 +1648,9 @@ static wave_desc diff_as_wave(const diff_desc* d) {
   w.sigma_max = 0.0;
   w.time_tile = d->time_tile;
   w.skew = d->skew;
-  w.tile_shape = d->tile_shape;
+  w.tile[0] = d->tile[0];
+  w.tile[1] = d->tile[1];
+  w.slab = d->slab;
   w.zchunks = d->zchunks;
   return w;
 }
@@ -1569,7 +1723,9 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
   char* p = (char*)state;
   c->w[0] = (float*)p;
   c->w[1] = (float*)(p + align_up(sizeof(float) * c->N));
-  s = apply_schedule(c, d->time_tile == 0 ? -1 : d->time_tile, d->skew, d->tile_shape, d->zchunks);
+  const int shape0 = tile_index(d->ndim, d->tile[0], d->tile[1]);
+  s = apply_schedule(c, d->time_tile == 0 ? -1 : d->time_tile, d->skew, shape0,
+                     d->time_tile == 0 ? 0 : d->slab, d->zchunks);
   if (s != WAVE_OK) {
     delete c;
     return s;
@@ -1584,7 +1740,7 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
   else Td = c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0);
   if (d->time_tile == 0 && Td > 0) {
     const int oshape = c->shape;
-    if (c->dim == 3 && d->tile_shape == 0) c->shape = 2;
+    if (c->dim == 3 && shape0 == 0) c->shape = 2;
     Plan pl;
     if (make_plan(c, KIND_TILED, Td, pl) == WAVE_OK) c->T = Td;
     else c->shape = oshape;
@@ -1613,6 +1769,41 @@ wave_status diff_forward(wave_ctx* c, int32_t nt, const float* u0, float* u_out)
     if (overlap(u0, c->w[i]) || overlap(u_out, c->w[i]))
       return fail(c, WAVE_EINVAL, "u0 and u_out must not overlap the context's state");
   if (nt == 0) return copy(c, u0, u_out, c->N);
+  if (c->T >= 1 && c->slab > 0) {
+    // The skewed schedule (see run_steps_skewed).  Level l lives in u0
+    // (l = 0), u_out (l = nt) or state level (l - 1) % 2: level l + 1
+    // overwrites level l - 1, whose last reader (step l - 1 of a later slab,
+    // planes from (j+1)Z - (k-1)s - r on) lies beyond what the write reaches
+    // ((j+1)Z - ks) since s >= r.
+    auto buf = [&](int l) -> float* { return l == 0 ? (float*)u0 : (l == nt ? u_out : c->w[(l - 1) & 1]); };
+    const int64_t sk = c->skew, Z = c->slab;
+    int done = 0;
+    while (done < nt) {
+      const int Tw = std::min(c->T, nt - done);
+      const int64_t J = (c->n0 + (int64_t)(Tw - 1) * sk + Z - 1) / Z;
+      for (int64_t j = 0; j < J; ++j) {
+        for (int k = 0; k < Tw; ++k) {
+          const int64_t lo = std::max<int64_t>(0, j * Z - k * sk);
+          const int64_t hi = std::min<int64_t>(c->n0, (j + 1) * Z - k * sk);
+          if (lo >= hi) continue;
+          Plan p;
+          wave_status s = make_plan(c, KIND_UNTILED, 1, p, lo, hi);
+          if (s != WAVE_OK) return s;
+          SweepArgs A = base_args(c);
+          A.cur = buf(done + k);
+          A.prev = A.cur;   // not read in this mode
+          A.b = A.cur;      // not read in this mode
+          A.outA = buf(done + k + 1);
+          A.outB = nullptr;
+          A.step0 = done + k;
+          A.dir = 1;
+          if ((s = launch_window(c, p, A))) return s;
+        }
+      }
+      done += Tw;
+    }
+    return WAVE_OK;
+  }
   const bool untiled = c->T < 0;
   const float* src = u0;
   int k = 0, done = 0;

@@ -152,6 +152,8 @@ struct SweepArgs {
   int32_t ntiles;              // tiles per axis-0 segment
   int32_t nblocks;             // ntiles * number of axis-0 segments (1D grid)
   int32_t zchunk;              // streamed-axis segment length per block
+  int32_t zlo, zhi;            // planes [zlo, zhi) this launch updates (the whole grid, or one
+                               // slab of the skewed schedule); segments of zchunk planes from zlo
 };
 
 // LDS planes of the tiled kernel: each is (EX + 2R) x (EY + 2R_y) floats; one

@@ -254,8 +254,8 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
   work_item(A, blk, tile, chunk);
   const int ty = tile / A.tiles_x, tx = tile % A.tiles_x;
   const int gy0 = ty * TY, gx0 = tx * TX;
-  const int za = chunk * A.zchunk;
-  const int zb = min(za + A.zchunk, A.n0);
+  const int za = A.zlo + chunk * A.zchunk;
+  const int zb = min(za + A.zchunk, A.zhi);
   const int n0 = A.n0;
   Seg sg;
   sg.lo = max(0, za - R);
@@ -491,7 +491,9 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
 
 // --------------------------------------------------------------- time-tiled sweep
 
-template <int R, int T, int DIM, int MODE, int NW, int RY, bool BATCH>
+// 3D: the NW waves form NW/NWX rows of NWX waves; wave (wy, wx) owns rows
+// wy*RY .. wy*RY+RY-1 and columns wx*64 .. wx*64+63 of the extended tile.
+template <int R, int T, int DIM, int MODE, int NW, int RY, int NWX, bool BATCH>
 __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::type P) {
   int blk;
   const SweepArgs& A = shot_args(P, blk);
@@ -499,8 +501,11 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
   constexpr bool DF = (MODE == MODE_DIFF);   // diffusion: one input level, no b
   constexpr int W = 2 * R + 1;
   constexpr bool ROT = W <= kMaxUnrollW;
-  constexpr int EY = HY ? NW * RY : 1;
-  constexpr int EX = HY ? 64 : 64 * NW * RY;
+  static_assert(HY || NWX == 1, "2D tiles are one row of waves");
+  static_assert(NW % NWX == 0, "waves must fill whole rows");
+  constexpr int NWY = NW / NWX;
+  constexpr int EY = HY ? NWY * RY : 1;
+  constexpr int EX = HY ? 64 * NWX : 64 * NW * RY;
   constexpr int RYH = HY ? R : 0;
   constexpr int LDW = EX + 2 * R;
   constexpr int PL = tiled_plane_floats(R, EY, EX, HY);
@@ -510,6 +515,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
 
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int wy = wv / NWX, wx = wv % NWX;                              // 3D wave row / column
   const int H = A.skew * T;
   const int HYH = HY ? H : 0;
   const int CY = HY ? EY - 2 * H : 1;
@@ -518,8 +524,8 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
   work_item(A, blk, tile, chunk);
   const int ty = tile / A.tiles_x, tx = tile % A.tiles_x;
   const int gy0 = ty * CY - HYH, gx0 = tx * CX - H;
-  const int za = chunk * A.zchunk;
-  const int zb = min(za + A.zchunk, A.n0);
+  const int za = A.zlo + chunk * A.zchunk;
+  const int zb = min(za + A.zchunk, A.zhi);
   const int n0 = A.n0;
   Seg sg;
   sg.lo = max(0, za - (T + 1) * R);
@@ -538,11 +544,11 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
   uint32_t col[RY];
   bool xcore[HY ? 1 : RY];
   float stx[HY ? 1 : RY];
-  const int lid0 = (HY ? wv * RY + RYH : 0) * LDW + (HY ? lane : wv * RY * 64 + lane) + R;
+  const int lid0 = (HY ? wy * RY + RYH : 0) * LDW + (HY ? wx * 64 + lane : wv * RY * 64 + lane) + R;
 #pragma unroll
   for (int i = 0; i < RY; ++i) {
-    const int ly = HY ? wv * RY + i : 0;
-    const int lx = HY ? lane : (wv * RY + i) * 64 + lane;
+    const int ly = HY ? wy * RY + i : 0;
+    const int lx = HY ? wx * 64 + lane : (wv * RY + i) * 64 + lane;
     const int gy = gy0 + ly, gx = gx0 + lx;
     const bool yin = gy >= 0 && gy < A.n1, xin = gx >= 0 && gx < A.n2;
     col[i] = (yin && xin) ? (uint32_t)(gy * (int)A.s1 + gx) * 4u : kOOB;
@@ -551,7 +557,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
       stx[HY ? 0 : i] = A.has_damp ? damp_term(gx, A.n2, A.nbl, A.st_coef) : 0.0f;
     }
   }
-  const int wrow0 = HY ? wv * RY : 0;   // first row of this wave (3D)
+  const int wrow0 = HY ? wy * RY : 0;   // first row of this wave (3D)
 
   float win[T][RY][W];
 #pragma unroll
@@ -661,7 +667,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
         const rsrc_t rh = HIST ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
         const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ra;
         float v[RY], st[RY], upv[RY], fr[RY];
-        const int ybase = gy0 + (HY ? wrow0 : 0), xbase = gx0 + (HY ? 0 : wv * RY * 64);
+        const int ybase = gy0 + (HY ? wrow0 : 0), xbase = gx0 + (HY ? wx * 64 : wv * RY * 64);
         if (EV && fz) forcing_rows<RY, HY>(A, zk, ybase, xbase, lane, step, fr);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {

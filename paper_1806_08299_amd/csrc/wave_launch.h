@@ -11,8 +11,11 @@ enum : int { KIND_UNTILED = 0, KIND_TILED = 1 };
 //   3D untiled        4 waves x 4 rows       -> 16 x 64 core (256 threads)
 //   3D tiled, shape 1 8 waves x 8 rows       -> 64 x 64 extended tile (512 threads)
 //   3D tiled, shape 2 8 waves x 4 rows       -> 32 x 64 extended tile (512 threads)
+//   3D tiled, shape 3 8 x 2 waves x 4 rows   -> 32 x 128 extended tile (1024 threads)
+//   3D tiled, shape 4 4 x 2 waves x 4 rows   -> 16 x 128 extended tile (512 threads)
 //   2D (both)         4 waves x 4 segments   -> 1 x 1024 (256 threads)
 struct BlockShape { int nw, ry, ey, ex; };
+constexpr int kNumShapes3D = 4;
 // Untiled 3D block: waves x rows per thread (core 16 x 64 by default).
 #ifndef WAVE_UNTILED_NW
 #define WAVE_UNTILED_NW 4
@@ -59,6 +62,11 @@ constexpr int kBatchTmax = 2;
 // a (2R+1)-plane window per column.
 constexpr int kTmax3D_S1[9] = {0, 4, 4, 3, 2, 2, 2, 1, 1};
 constexpr int kTmax3D_S2[9] = {0, 6, 6, 4, 3, 2, 2, 2, 1};
+// 32 x 128: 1024 threads leave 128 registers per thread (half of the
+// 512-thread tiles), so the windows of fewer levels fit (deeper builds spill).
+constexpr int kTmax3D_S3[9] = {0, 2, 2, 1, 1, 1, 1, 1, 1};
+// 16 x 128: bounded by the core, 16 - 2 r T >= 1 rows.
+constexpr int kTmax3D_S4[9] = {0, 6, 3, 2, 1, 1, 1, 1, 0};
 constexpr int kTmax2D[9] = {0, 4, 4, 4, 4, 2, 2, 2, 2};
 
 }  // namespace wavett

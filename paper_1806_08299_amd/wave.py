@@ -38,11 +38,56 @@ class wave_desc(ctypes.Structure):
                 ("shape", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3),
                 ("dt", ctypes.c_double), ("nbl", ctypes.c_int32), ("sigma_max", ctypes.c_double),
                 ("time_tile", ctypes.c_int32), ("skew", ctypes.c_int32),
-                ("tile_shape", ctypes.c_int32), ("zchunks", ctypes.c_int32)]
+                ("tile", ctypes.c_int32 * 2), ("slab", ctypes.c_int32), ("zchunks", ctypes.c_int32)]
+
+
+class Schedule(tuple):
+    """(T, skew, tile_shape, zchunks, tile, slab): tile_shape is the index of
+    the extended tile in the table of built tiles (0 when the schedule is
+    untiled or skewed), tile its (rows, columns), slab the slab thickness of
+    the skewed schedule (0: not skewed)."""
+    __slots__ = ()
+    _names = ("T", "skew", "tile_shape", "zchunks", "tile", "slab")
+
+    def __new__(cls, *v):
+        return tuple.__new__(cls, v)
+
+    def __getattr__(self, k):
+        try:
+            return self[self._names.index(k)]
+        except ValueError:
+            raise AttributeError(k)
+
+    def asdict(self):
+        return dict(zip(self._names, self))
+
+
+def tile_table(ndim: int):
+    """Extended tiles (rows, columns) of the register-tiled sweep, index 1.."""
+    out = []
+    i = 1
+    while True:
+        ey, ex = ctypes.c_int32(), ctypes.c_int32()
+        if lib().wave_tile_extent(ndim, i, ctypes.byref(ey), ctypes.byref(ex)) != WAVE_OK:
+            return out
+        out.append((ey.value, ex.value))
+        i += 1
+
+
+def _tile_of(ndim, tile_shape, tile):
+    """Extents for a table index (0 = automatic) or explicit extents."""
+    if tile is not None:
+        return (int(tile[0]), int(tile[1]))
+    if not tile_shape or ndim == 2:   # 2D has one tile: the index is ignored
+        return (0, 0)
+    tab = tile_table(ndim)
+    if not 1 <= tile_shape <= len(tab):
+        raise WaveError(-7, "no tile %d in the table of built tiles" % tile_shape)
+    return tab[tile_shape - 1]
 
 
 def make_desc(shape, spacing, dt, space_order, nbl=0, sigma_max=0.0, time_tile=-1, skew=0,
-              tile_shape=0, zchunks=0) -> wave_desc:
+              tile_shape=0, zchunks=0, tile=None, slab=0) -> wave_desc:
     d = wave_desc()
     shape = tuple(int(s) for s in shape)
     d.ndim = len(shape)
@@ -56,7 +101,8 @@ def make_desc(shape, spacing, dt, space_order, nbl=0, sigma_max=0.0, time_tile=-
     d.sigma_max = float(sigma_max)
     d.time_tile = int(time_tile)
     d.skew = int(skew)
-    d.tile_shape = int(tile_shape)
+    d.tile[0], d.tile[1] = _tile_of(d.ndim, tile_shape, tile)
+    d.slab = int(slab)
     d.zchunks = int(zchunks)
     return d
 
@@ -66,11 +112,11 @@ class diff_desc(ctypes.Structure):
                 ("shape", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3),
                 ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("time_tile", ctypes.c_int32), ("skew", ctypes.c_int32),
-                ("tile_shape", ctypes.c_int32), ("zchunks", ctypes.c_int32)]
+                ("tile", ctypes.c_int32 * 2), ("slab", ctypes.c_int32), ("zchunks", ctypes.c_int32)]
 
 
 def make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile=-1, skew=0, tile_shape=0,
-                   zchunks=0) -> diff_desc:
+                   zchunks=0, tile=None, slab=0) -> diff_desc:
     d = diff_desc()
     shape = tuple(int(s) for s in shape)
     d.ndim = len(shape)
@@ -83,7 +129,8 @@ def make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile=-1, skew=0,
     d.alpha = float(alpha)
     d.time_tile = int(time_tile)
     d.skew = int(skew)
-    d.tile_shape = int(tile_shape)
+    d.tile[0], d.tile[1] = _tile_of(d.ndim, tile_shape, tile)
+    d.slab = int(slab)
     d.zchunks = int(zchunks)
     return d
 
@@ -105,15 +152,15 @@ def lib():
             "wave_state_bytes": (sz, [P]),
             "wave_init": (i32, [P, P, P, sz, P, ctypes.POINTER(P)]),
             "wave_set_model": (i32, [P, P]),
-            "wave_set_schedule": (i32, [P, i32, i32, i32, i32]),
-            "wave_get_schedule": (i32, [P, P, P, P, P]),
+            "wave_set_schedule": (i32, [P, i32, i32, P, i32, i32]),
+            "wave_get_schedule": (i32, [P, P, P, P, P, P]),
             "wave_scratch_bytes": (sz, [P, i32, i32, i32, i32, i32]),
             "wave_forward": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, P, sz]),
             "wave_forward_static": (i32, [P, i32, i32, P, P, i32, P, P, P, P]),
             "wave_adjoint_grad": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, i32, P, sz]),
             "wave_batch": (i32, [P, i32, i32, P, P, P, P, P, P, P, P, i32, P, P]),
             "wave_autotune": (i32, [P, i32, i32, i32, P, sz, P]),
-            "wave_tiled_max_depth": (i32, [i32, i32, i32]),
+            "wave_tiled_max_depth": (i32, [i32, i32, i32, i32]),
             "wave_tile_extent": (i32, [i32, i32, P, P]),
             "wave_ai_naive": (dbl, [dbl, i32]),
             "wave_ai_tight": (dbl, [dbl, i32, i32, P, P, P, dbl]),
@@ -189,14 +236,26 @@ def wave_set_model(ctx, m: torch.Tensor):
     _check(lib().wave_set_model(ctx, _dptr(m)), ctx)
 
 
-def wave_set_schedule(ctx, time_tile: int, skew: int = 0, tile_shape: int = 0, zchunks: int = 0):
-    _check(lib().wave_set_schedule(ctx, time_tile, skew, tile_shape, zchunks), ctx)
+def wave_set_schedule(ctx, time_tile: int, skew: int = 0, tile_shape: int = 0, zchunks: int = 0, tile=None,
+                      slab: int = 0, ndim: int = 3):
+    """time_tile, skew, the extended tile (a table index tile_shape, or
+    extents tile=(rows, columns)), slab (> 0: the skewed schedule) and the
+    number of axis-0 segments."""
+    ext = (ctypes.c_int32 * 2)(*_tile_of(ndim, tile_shape, tile))
+    _check(lib().wave_set_schedule(ctx, int(time_tile), int(skew), ext, int(slab), int(zchunks)), ctx)
 
 
-def wave_get_schedule(ctx):
-    v = [ctypes.c_int32() for _ in range(4)]
-    _check(lib().wave_get_schedule(ctx, *[ctypes.byref(x) for x in v]), ctx)
-    return tuple(x.value for x in v)
+def wave_get_schedule(ctx, ndim: int = 3) -> Schedule:
+    T, sk, sl, zc = (ctypes.c_int32() for _ in range(4))
+    ext = (ctypes.c_int32 * 2)()
+    _check(lib().wave_get_schedule(ctx, ctypes.byref(T), ctypes.byref(sk), ext, ctypes.byref(sl),
+                                   ctypes.byref(zc)), ctx)
+    tile = (ext[0], ext[1])
+    idx = 0
+    if tile != (0, 0):
+        tab = tile_table(ndim)
+        idx = tab.index(tile) + 1 if tile in tab else 0
+    return Schedule(T.value, sk.value, idx, zc.value, tile, sl.value)
 
 
 def wave_scratch_bytes(ctx, nt: int, nsrc: int, nrec: int, ckpt_every: int = 0, adjoint: int = 0) -> int:
@@ -303,14 +362,18 @@ class ShotBatch:
         return self.rec_out, self.grad
 
 
-def wave_tiled_max_depth(space_order: int, ndim: int, tile_shape: int = 1) -> int:
-    return int(lib().wave_tiled_max_depth(space_order, ndim, tile_shape))
+def wave_tiled_max_depth(space_order: int, ndim: int, tile_shape: int = 1, tile=None) -> int:
+    """Deepest register-tiled depth built for the order and the extended tile
+    (table index tile_shape, or extents tile)."""
+    ey, ex = _tile_of(ndim, tile_shape if ndim == 3 else 1, tile)
+    return int(lib().wave_tiled_max_depth(space_order, ndim, ey, ex))
 
 
 def block_extent(ndim: int, tile_shape: int = 1):
-    """(ey, ex) columns loaded by one workgroup of the time-tiled sweep."""
+    """(ey, ex) columns loaded by one workgroup of the time-tiled sweep for
+    entry tile_shape of the table of built tiles."""
     ey, ex = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().wave_tile_extent(ndim, tile_shape, ctypes.byref(ey), ctypes.byref(ex)), None)
+    _check(lib().wave_tile_extent(ndim, tile_shape if ndim == 3 else 1, ctypes.byref(ey), ctypes.byref(ex)), None)
     return ey.value, ex.value
 
 
@@ -363,9 +426,9 @@ class WaveOp:
     """A context plus the device buffers it needs (allocated as torch tensors)."""
 
     def __init__(self, shape, spacing, dt, space_order, m: torch.Tensor, nbl=0, sigma_max=0.0,
-                 time_tile=-1, skew=0, tile_shape=0, zchunks=0, device="cuda"):
+                 time_tile=-1, skew=0, tile_shape=0, zchunks=0, device="cuda", tile=None, slab=0):
         self.desc = make_desc(shape, spacing, dt, space_order, nbl, sigma_max, time_tile, skew,
-                              tile_shape, zchunks)
+                              tile_shape, zchunks, tile=tile, slab=slab)
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
         self.device = torch.device(device)
@@ -397,11 +460,11 @@ class WaveOp:
         self.m = m.to(self.device, torch.float32).contiguous()
         wave_set_model(self.ctx, self.m)
 
-    def set_schedule(self, time_tile, skew=0, tile_shape=0, zchunks=0):
-        wave_set_schedule(self.ctx, time_tile, skew, tile_shape, zchunks)
+    def set_schedule(self, time_tile, skew=0, tile_shape=0, zchunks=0, tile=None, slab=0):
+        wave_set_schedule(self.ctx, time_tile, skew, tile_shape, zchunks, tile=tile, slab=slab, ndim=self.ndim)
 
-    def schedule(self):
-        return wave_get_schedule(self.ctx)
+    def schedule(self) -> Schedule:
+        return wave_get_schedule(self.ctx, self.ndim)
 
     def forward(self, nt, src_xyz=None, wavelet=None, rec_xyz=None, u_init=None, want_final=False,
                 ckpt_every=0, adjoint_scratch=False):
@@ -483,8 +546,9 @@ class DiffOp:
     on the sweep engine: a diffusion context plus its two-level state."""
 
     def __init__(self, shape, spacing, dt, alpha, space_order, time_tile=-1, skew=0, tile_shape=0, zchunks=0,
-                 device="cuda"):
-        self.desc = make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile, skew, tile_shape, zchunks)
+                 device="cuda", tile=None, slab=0):
+        self.desc = make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile, skew, tile_shape, zchunks,
+                                   tile=tile, slab=slab)
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
         self.device = torch.device(device)
@@ -504,11 +568,11 @@ class DiffOp:
     def npts(self):
         return int(np.prod(self.shape))
 
-    def set_schedule(self, time_tile, skew=0, tile_shape=0, zchunks=0):
-        wave_set_schedule(self.ctx, time_tile, skew, tile_shape, zchunks)
+    def set_schedule(self, time_tile, skew=0, tile_shape=0, zchunks=0, tile=None, slab=0):
+        wave_set_schedule(self.ctx, time_tile, skew, tile_shape, zchunks, tile=tile, slab=slab, ndim=self.ndim)
 
-    def schedule(self):
-        return wave_get_schedule(self.ctx)
+    def schedule(self) -> Schedule:
+        return wave_get_schedule(self.ctx, self.ndim)
 
     def autotune(self, trial_steps: int = 8, repeats: int = 2, max_T: int = 0) -> float:
         """Time the schedules (wave_autotune) and keep the fastest; returns

@@ -141,3 +141,37 @@ def test_tight_estimator_invariants(W):
     b2 = 2 * 4 / 512 * np.floor(512 / 32)
     u = b1 + b2 - b1 * b2
     assert got == pytest.approx(S * T / (1 + u), rel=1e-14)
+
+
+def test_tile_table_and_depth_limits(W):
+    """The run-time extended tiles come from a table of built tiles; every
+    entry leaves a core at its deepest depth, and extents outside the table
+    have no depth."""
+    assert W.tile_table(3) == [(64, 64), (32, 64), (32, 128), (16, 128)]
+    assert W.tile_table(2) == [(1, 1024)]
+    for so in range(2, 17, 2):
+        r = so // 2
+        for ey, ex in W.tile_table(3):
+            T = W.wave_tiled_max_depth(so, 3, tile=(ey, ex))
+            assert T >= 0
+            if T:
+                assert ey - 2 * r * T >= 1 and ex - 2 * r * T >= 1, (so, ey, ex, T)
+        assert W.wave_tiled_max_depth(so, 3, tile=(48, 64)) == 0
+        assert W.wave_tiled_max_depth(so, 3, tile=(0, 0)) == 0
+    assert W.wave_tiled_max_depth(8, 3, tile=(32, 64)) == 3
+    assert W.wave_tiled_max_depth(16, 3, tile=(16, 128)) == 0
+    assert W.wave_tiled_max_depth(4, 2, tile=(1, 1024)) == 4
+    assert W.block_extent(3, 3) == (32, 128)
+
+
+def test_descriptor_tile_and_slab_validation(W):
+    ok = W.make_desc((64, 64, 64), 10.0, 1e-3, 8, time_tile=2, tile=(32, 128))
+    assert W.wave_state_bytes(ok) > 0
+    sk = W.make_desc((64, 64, 64), 10.0, 1e-3, 8, time_tile=4, slab=48)
+    assert W.wave_state_bytes(sk) > 0
+    bad = W.make_desc((64, 64, 64), 10.0, 1e-3, 8, time_tile=2, tile=(32, 128))
+    bad.tile[0] = 48                     # not a built tile: rejected by validation
+    assert W.wave_state_bytes(bad) == 0
+    neg = W.make_desc((64, 64, 64), 10.0, 1e-3, 8, time_tile=2, slab=0)
+    neg.slab = -3
+    assert W.wave_state_bytes(neg) == 0
