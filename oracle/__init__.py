@@ -97,8 +97,9 @@ def lib():
         L.og_adjoint.argtypes = [P, P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P,
                                  P, P, P, P, ctypes.c_int, P]
         L.og_diffuse.argtypes = [P, ctypes.c_double, ctypes.c_int, P, P]
+        L.og_diffuse_ab2.argtypes = [P, ctypes.c_double, ctypes.c_int, P, P]
         for f in (L.og_fd_coeffs, L.og_laplacian, L.og_sigma, L.og_interp_corners,
-                  L.og_forward, L.og_adjoint, L.og_diffuse):
+                  L.og_forward, L.og_adjoint, L.og_diffuse, L.og_diffuse_ab2):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -216,4 +217,16 @@ def diffuse(g: Grid, a: float, nt: int, u0) -> np.ndarray:
     gc = g.c()
     if lib().og_diffuse(ctypes.byref(gc), float(a), int(nt), _p(u0), _p(out)) != 0:
         raise ValueError("og_diffuse failed")
+    return out
+
+
+def diffuse_ab2(g: Grid, a: float, nt: int, u0) -> np.ndarray:
+    """The same operator with a two-level time dependence: nt steps of the
+    two-step Adams-Bashforth rule u <- u + dt a (3/2 L u^n - 1/2 L u^{n-1})
+    from u0, with u^{-1} = u^0 (g.dt is the step)."""
+    u0 = _f64(u0, g.shape)
+    out = np.empty_like(u0)
+    gc = g.c()
+    if lib().og_diffuse_ab2(ctypes.byref(gc), float(a), int(nt), _p(u0), _p(out)) != 0:
+        raise ValueError("og_diffuse_ab2 failed")
     return out
