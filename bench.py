@@ -26,7 +26,19 @@ on one JSON line (progress goes to stderr):
 * laplace: the paper's second workload, explicit diffusion on 500^3 x 32
   and 600^3 x 16 steps at space orders 2..16, default, best untiled and best
   time-tiled schedule with their algorithmic HBM rates;
-* cpu_baseline: the FP64 oracle on the host cores on a bounded sample.
+* point_source_64: the 64^3 space-order-4 100-step problem, untiled,
+  register-tiled T = 1, 2, 4 and skewed, each with its roofline fraction
+  (the working set fits the last-level cache);
+* depth_sweep: the headline workload at every time-tile depth T = 1..8,
+  register-tiled (where built) and skewed, with algorithmic rates;
+* smooth_768: the 768^3 (+40 = 848^3) smooth-model problem at space orders
+  12 and 16 (500 steps), autotuned, untiled and best time-tiled;
+* wave2d: 16384^2 at space orders 2, 4, 8 (100 steps), untiled against the
+  best register-tiled and skewed schedules;
+* two_level_laplace: the Laplace operator with a two-level time dependence
+  (two-step Adams-Bashforth) on 500^3 x 32 steps, untiled against skewed,
+  beside the one-level step at the same time step;
+* cpu_baseline: the FP64 oracle on the host cores on bounded samples.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--quick]
 """
@@ -77,13 +89,13 @@ def traffic_record(workload: str, sched) -> dict | None:
     if not os.path.exists(path):
         return None
     sha = kernel_sources_sha()
-    T, _, shape, zc = sched
+    T, shape, zc, slab = sched[0], sched[2], sched[3], sched[5]
     for line in open(path):
         if not line.startswith("record "):
             continue
         kv = dict(f.split("=", 1) for f in line.split()[1:])
         if (kv.get("workload") == workload and int(kv["T"]) == T and int(kv["shape"]) == shape
-                and int(kv["zchunks"]) == zc and kv.get("sources") == sha):
+                and int(kv["zchunks"]) == zc and int(kv.get("slab", 0)) == slab and kv.get("sources") == sha):
             return kv
     return None
 
@@ -130,10 +142,12 @@ def autotune(op, trial_steps=40):
 
 
 def kernel_name(sched, so) -> str:
-    T, _, shape, _ = sched
+    T, slab, tile = sched[0], sched[5], sched[4]
     if T < 0:
         return "k_untiled R=%d (single-step sweep)" % (so // 2)
-    return "k_tiled R=%d T=%d tile_shape=%d" % (so // 2, T, shape)
+    if slab > 0:
+        return "k_untiled R=%d (single-step sweep) in the skewed schedule, T=%d, slab %d" % (so // 2, T, slab)
+    return "k_tiled R=%d T=%d tile %dx%d" % (so // 2, T, tile[0], tile[1])
 
 
 def _cpu_model() -> str:
@@ -144,6 +158,26 @@ def _cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def _physical_cores(cpus) -> int:
+    """Distinct (package, core) pairs among the logical CPUs `cpus`, from
+    /proc/cpuinfo (0 if it cannot be read)."""
+    cur, pairs = {}, {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if "processor" in cur:
+                    pairs[int(cur["processor"])] = (cur.get("physical id", "0"), cur.get("core id", cur["processor"]))
+                cur = {}
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            cur[k] = v
+        if "processor" in cur:
+            pairs[int(cur["processor"])] = (cur.get("physical id", "0"), cur.get("core id", cur["processor"]))
+    except OSError:
+        return 0
+    return len({pairs[c] for c in cpus if c in pairs})
 
 
 _ORACLE_ONE_THREAD = r"""
@@ -159,17 +193,21 @@ print(json.dumps({"s": time.perf_counter() - t0, "npts": int(w.npts)}))
 """
 
 
-def cpu_baseline(w, budget_s=20.0, n=512):
-    """FP64 oracle on the host: the same grid, model, order and source for a
-    few time steps (bounded to ~budget_s of CPU work), as Gpts/s, on all the
-    threads OpenMP is given; plus one step on one thread (a child process
-    with OMP_NUM_THREADS=1)."""
+def cpu_baseline(w, budget_s=20.0, n=512, quick=False):
+    """FP64 oracle on the host: the headline grid, model, order and source for
+    a few time steps (bounded to ~budget_s of CPU work), as Gpts/s, on all the
+    threads OpenMP is given; one step of it on one thread (a child process
+    with OMP_NUM_THREADS=1); the 64^3 point-source problem complete; the
+    gradient problem (forward with history, adjoint with imaging) on a bounded
+    slice of its steps."""
     import subprocess
     import oracle
+    import waveinputs as wi
     oracle.build(force=False)
     g = oracle.Grid(w.shape, w.spacing, w.dt, w.so, nbl=w.nbl, sigma_max=w.sigma_max)
     m = w.m.astype(np.float64)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    cpus = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else list(range(os.cpu_count()))
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(cpus)
     t0 = time.perf_counter()
     oracle.forward(g, m, 1, w.src_xyz, w.wavelet[:1].astype(np.float64), w.rec_xyz)
     t1 = time.perf_counter() - t0
@@ -180,7 +218,8 @@ def cpu_baseline(w, budget_s=20.0, n=512):
     out = {"value": round(w.npts * steps / dt / 1e9, 4), "unit": "Gpts/s", "cores": threads, "kind": "oracle",
            "sample": "%s: first %d of %d time steps on the full %s grid (FP64, OpenMP over axis 0), "
                      "%.1f s" % (w.name, steps, w.nt, "x".join(map(str, w.shape)), dt),
-           "cpu_model": _cpu_model(), "logical_cpus": os.cpu_count()}
+           "threads": threads, "physical_cores": _physical_cores(cpus), "logical_cpus_available": len(cpus),
+           "cpu_model": _cpu_model()}
     env = dict(os.environ, OMP_NUM_THREADS="1")
     try:
         r = subprocess.run([sys.executable, "-c", _ORACLE_ONE_THREAD, ROOT, str(n)], env=env, capture_output=True,
@@ -191,6 +230,28 @@ def cpu_baseline(w, budget_s=20.0, n=512):
     except Exception as e:   # the single-thread figure is context only
         out["single_thread_value"] = None
         out["single_thread_sample"] = "not measured: %s" % type(e).__name__
+    # the 64^3 point-source problem, complete
+    c1 = wi.point_source_64()
+    g1 = oracle.Grid(c1.shape, c1.spacing, c1.dt, c1.so)
+    t0 = time.perf_counter()
+    oracle.forward(g1, c1.m.astype(np.float64), c1.nt, c1.src_xyz, c1.wavelet.astype(np.float64), c1.rec_xyz)
+    d1 = time.perf_counter() - t0
+    out["point_source_64"] = {"value": round(c1.npts * c1.nt / d1 / 1e9, 4), "unit": "Gpts/s",
+                              "sample": "complete: %d steps on 64^3, %.2f s" % (c1.nt, d1)}
+    # the gradient problem: forward with history + adjoint with imaging on a
+    # slice of its steps (the complete 2000-step run takes about 15 CPU-minutes)
+    n4 = 96 if quick else 256
+    G = wi.gradient_256(nt=2000, n=n4)["init"]
+    g4 = oracle.Grid(G.shape, G.spacing, G.dt, G.so, nbl=G.nbl, sigma_max=G.sigma_max)
+    k = 12
+    m4 = G.m.astype(np.float64)
+    t0 = time.perf_counter()
+    fw = oracle.forward(g4, m4, k, G.src_xyz, G.wavelet[:k].astype(np.float64), G.rec_xyz, want_hist=True)
+    oracle.adjoint(g4, m4, k, np.ones_like(fw["rec"]), hist=fw["hist"], src_xyz=G.src_xyz, rec_xyz=G.rec_xyz)
+    d4 = time.perf_counter() - t0
+    out["gradient_256"] = {"value": round(G.npts * k / d4 / 1e9, 4), "unit": "Gpts/s (forward + adjoint per step)",
+                           "sample": "%d of %d steps of forward with history and adjoint with imaging on %s, "
+                                     "%.1f s" % (k, G.nt, "x".join(map(str, G.shape)), d4)}
     return out
 
 
@@ -236,15 +297,28 @@ def gradient_bench(args, dev, stream):
         return best, gm
 
     (tf, ta), gm = one(tuned)
-    out.update({"schedule": dict(zip(("T", "skew", "tile_shape", "zchunks"), tuned)),
+    out.update({"schedule": sched_dict(tuned),
                 "value": round(init.npts * init.nt / (tf + ta) / 1e9, 2),
                 "forward_with_checkpoints_s": round(tf, 4), "recompute_plus_adjoint_s": round(ta, 4),
                 "grad_finite": bool(torch.isfinite(gm).all().item())})
-    # adjoint launch: recompute (history) + adjoint per segment; the adjoint
-    # kernel's algorithmic bytes per point-update
+    # Roofline of the two phases: algorithmic bytes of their sweeps (forward
+    # 16 B or 20/T B per point-update; recompute storing the history + 4 B;
+    # adjoint with imaging + 12 B) over the phase's HIP-event time; the
+    # per-kernel split is in profiles/gradient_kernels_const2000_256cube_so8.txt.
     T = tuned[0]
-    out["adjoint_bytes_per_point_update"] = wave_bytes_per_point(T, 2)
-    out["history_bytes_per_point_update"] = wave_bytes_per_point(T, 1)
+    b_f, b_h, b_a = (wave_bytes_per_point(T, md) for md in (0, 1, 2))
+    nseg = -(-init.nt // K)
+    fwd_bytes = (b_f * init.nt + 8.0 * nseg) * init.npts            # + checkpoint copies (read + write a level)
+    adj_bytes = ((b_h + b_a) * init.nt + 8.0 * 2 * nseg) * init.npts  # + restoring the checkpoints
+    out["adjoint_bytes_per_point_update"] = b_a
+    out["history_bytes_per_point_update"] = b_h
+    out["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                       "forward_achieved": round(fwd_bytes / tf / 1e9, 1),
+                       "forward_frac": round(fwd_bytes / tf / 1e9 / HBM_PEAK_GBS, 4),
+                       "recompute_adjoint_achieved": round(adj_bytes / ta / 1e9, 1),
+                       "recompute_adjoint_frac": round(adj_bytes / ta / 1e9 / HBM_PEAK_GBS, 4),
+                       "bytes": "forward %.0f + checkpoint copies; recompute %.0f + adjoint %.0f B per point-update"
+                                % (b_f, b_h, b_a)}
     log("gradient %s: fwd %.3f s + recompute/adjoint %.3f s" % (tuned, tf, ta))
     if not args.no_untiled:
         (uf, ua), _ = one((-1, 0, 0, tuned[3] if tuned[0] < 0 else 0))
@@ -264,7 +338,7 @@ def batch_bench(args, dev, stream):
     import torch
     import waveinputs as wi
     from paper_1806_08299_amd import ShotBatch, WaveOp
-    from paper_1806_08299_amd.wave import wave_autotune, wave_scratch_bytes
+    from paper_1806_08299_amd.wave import wave_autotune, wave_bytes_per_point, wave_scratch_bytes
     if args.quick:
         S = wi.shot_batch(nshots=6, nt=100, sizes=[(64 + 16 * (i % 3), 64, 80) for i in range(6)], workers=8)
     else:
@@ -276,14 +350,17 @@ def batch_bench(args, dev, stream):
         op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
                     sigma_max=w.sigma_max, time_tile=-1)
         sc = op.scratch(wave_scratch_bytes(op.ctx, 20, 0, 0, 0, 0))
-        wave_autotune(op.ctx, 20, 1, 2, sc)          # batched kernels: untiled or T <= 2
+        wave_autotune(op.ctx, 20, 1, 16, sc)
+        if op.schedule().T > 2 and op.schedule().slab == 0:   # batched register tiles: T <= 2
+            wave_autotune(op.ctx, 20, 1, 2, sc)
         op._scratch = None
         ops.append(op)
         wavs.append(torch.from_numpy(w.wavelet).to(dev))
     npts = sum(w.npts for w in S)
     scheds = {}
     for op in ops:
-        key = "T=%d shape=%d" % (op.schedule()[0], op.schedule()[2])
+        sc_ = op.schedule()
+        key = "T=%d tile=%dx%d slab=%d" % (sc_.T, sc_.tile[0], sc_.tile[1], sc_.slab)
         scheds[key] = scheds.get(key, 0) + 1
 
     def timed(fn):
@@ -330,7 +407,17 @@ def batch_bench(args, dev, stream):
     torch.cuda.empty_cache()
     log("batch: batched forward %.3f s (first call %.3f s), gradient %.3f s (first call %.3f s)"
         % (t_fwd, t_first, tg, tg_first))
-    return {"workload": "shot_batch: %d shots, %d^3..%d^3 grids (%.1f Mpts in all), space orders 4/8, nt=%d, "
+    # algorithmic bytes: forward 16 B per point-update (20/T with a time
+    # tile); gradient: forward with checkpoints + recompute with history +
+    # adjoint with imaging, per shot with its own schedule
+    fb = sum(wave_bytes_per_point(op.schedule().T, 0) * w.npts for op, w in zip(ops, S)) * nt
+    gb = sum(sum(wave_bytes_per_point(op.schedule().T, md) for md in (0, 1, 2)) * w.npts
+             for op, w in zip(ops, S)) * nt
+    roof = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+            "forward_achieved": round(fb / t_fwd / 1e9, 1), "forward_frac": round(fb / t_fwd / 1e9 / HBM_PEAK_GBS, 4),
+            "gradient_achieved": round(gb / tg / 1e9, 1), "gradient_frac": round(gb / tg / 1e9 / HBM_PEAK_GBS, 4)}
+    return {"roofline": roof,
+            "workload": "shot_batch: %d shots, %d^3..%d^3 grids (%.1f Mpts in all), space orders 4/8, nt=%d, "
                         "gradient checkpoints every %d" % (len(S), round(min(w.npts for w in S) ** (1 / 3)),
                                                           round(max(w.npts for w in S) ** (1 / 3)), npts / 1e6, nt, K),
             "schedules": scheds, "unit": "Gpts/s",
@@ -342,35 +429,234 @@ def batch_bench(args, dev, stream):
                          "speedup_vs_sequential": round(tg_seq / tg, 3), "grad_finite": finite}}
 
 
-def tiling_factor(so, dev, stream, nt=100, n=512):
-    """Best untiled and best time-tiled schedule for the layered workload at
-    space order `so` (short runs, minimum of 2), and their ratio."""
+def sched_dict(sc) -> dict:
+    """JSON form of a schedule (T, skew, extended tile, slab, axis-0 segments)."""
+    return {"T": sc[0], "skew": sc[1], "tile": list(sc[4]), "slab": sc[5], "zchunks": sc[3]}
+
+
+def launches_per_step(sc, n0, nt) -> int:
+    """Sweep launches of one nt-step forward under schedule sc."""
+    T, skew, slab = sc[0], sc[1], sc[5]
+    if T < 1:
+        return nt
+    if slab == 0:
+        return -(-nt // T)
+    total, done = 0, 0
+    while done < nt:
+        Tw = min(T, nt - done)
+        J = -(-(n0 + (Tw - 1) * skew) // slab)
+        for j in range(J):
+            for k in range(Tw):
+                if max(0, j * slab - k * skew) < min(n0, (j + 1) * slab - k * skew):
+                    total += 1
+        done += Tw
+    return total
+
+
+def _rate(op, nt, w, wav, stream, reps=2, sched=None):
+    """Gpts/s of an nt-step forward (minimum over reps after one warm-up);
+    0 if the schedule is not available."""
+    import torch
+    from paper_1806_08299_amd import WaveError
+    if sched is not None:
+        try:
+            op.set_schedule(*sched[:4], tile=sched[4], slab=sched[5])
+        except WaveError:
+            return 0.0
+    op.forward(nt, w.src_xyz, wav, w.rec_xyz)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        op.forward(nt, w.src_xyz, wav, w.rec_xyz)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    return w.npts * nt / best / 1e9
+
+
+def _frac(gpts, T):
+    """Algorithmic GB/s and fraction of 8 TB/s at `gpts` point-updates/s for
+    depth T (compulsory bytes per point-update of the forward)."""
+    from paper_1806_08299_amd.wave import wave_bytes_per_point
+    gbs = gpts * wave_bytes_per_point(T, 0)
+    return round(gbs, 1), round(gbs / HBM_PEAK_GBS, 4)
+
+
+def _row(kind, gpts, sc):
+    gbs, fr = _frac(gpts, sc[0] if gpts else -1)
+    return {"kind": kind, "value": round(gpts, 1), "GBs": gbs, "frac": fr, "schedule": sched_dict(sc)}
+
+
+def c1_bench(dev, stream):
+    """64^3, space order 4, 100 steps (point source, receiver line): untiled,
+    register-tiled T = 1, 2, 4 (best tile) and skewed T = 2, 4, each with its
+    algorithmic rate.  The working set (five 1 MiB levels) fits the L2 and
+    the last-level cache, so the fractions of 8 TB/s are not HBM-limited."""
     import torch
     import waveinputs as wi
-    from paper_1806_08299_amd import WaveOp, WaveError
-    from paper_1806_08299_amd.wave import wave_tiled_max_depth
+    from paper_1806_08299_amd import WaveOp
+    from paper_1806_08299_amd.wave import Schedule, tile_table, wave_tiled_max_depth
+    w = wi.point_source_64()
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), time_tile=-1)
+    rows = []
+    best_u = max((_rate(op, w.nt, w, wav, stream, 3, Schedule(-1, 0, 0, zc, (0, 0), 0)), zc) for zc in (0, 1, 2, 4))
+    rows.append(_row("untiled", best_u[0], Schedule(-1, 4 // 2, 0, best_u[1], (0, 0), 0)))
+    for T in (1, 2, 4):
+        cands = [Schedule(T, 0, i + 1, zc, t, 0) for i, t in enumerate(tile_table(3))
+                 if wave_tiled_max_depth(w.so, 3, tile=t) >= T for zc in (0, 1, 2)]
+        if not cands:
+            rows.append({"kind": "register-tiled", "T": T, "value": None,
+                         "unsupported": "no register tile holds depth %d at space order %d" % (T, w.so)})
+            continue
+        r = max((_rate(op, w.nt, w, wav, stream, 3, c), c) for c in cands)
+        rows.append(_row("register-tiled", r[0], r[1]))
+    for T in (2, 4):
+        r = max((_rate(op, w.nt, w, wav, stream, 3, Schedule(T, 0, 0, zc, (0, 0), Z)), Schedule(T, 2, 0, zc, (0, 0), Z))
+                for Z in (8, 16, 32) for zc in (0, 1))
+        rows.append(_row("skewed", r[0], r[1]))
+    del op
+    torch.cuda.empty_cache()
+    return {"workload": "%s, model %s, nt=%d, 64 receivers" % (w.name, "x".join(map(str, w.shape)), w.nt),
+            "unit": "Gpts/s", "note": "working set 5 MiB: served by the L2 and the last-level cache, "
+                                      "so the fraction of 8 TB/s is not an HBM-bound figure", "rows": rows}
+
+
+def depth_sweep(op, w, wav, stream, nt=40):
+    """The headline workload at every time-tile depth T = 1..8: the best
+    register-tiled schedule over the tiles that hold T (or why none does)
+    and the best skewed schedule, on an nt-step slice, with algorithmic
+    rates (20/T B per point-update, 16 at T = 1)."""
+    from paper_1806_08299_amd.wave import Schedule, tile_table, wave_tiled_max_depth
+    rows = []
+    tab = tile_table(3)
+    for T in range(1, 9):
+        row = {"T": T}
+        cands = [Schedule(T, 0, i + 1, zc, t, 0) for i, t in enumerate(tab)
+                 if wave_tiled_max_depth(w.so, 3, tile=t) >= T for zc in (0, 16)]
+        if cands:
+            r = max((_rate(op, nt, w, wav, stream, 1, c), c) for c in cands)
+            row["register_tiled"] = _row("register-tiled", r[0], r[1])
+        else:
+            row["register_tiled"] = {"value": None, "unsupported":
+                                     "not built: every fused level keeps a %d-plane window per column in registers, "
+                                     "and no tile of the table holds %d levels at space order %d"
+                                     % (w.so + 1, T, w.so)}
+        if T >= 2:
+            r = max((_rate(op, nt, w, wav, stream, 1, Schedule(T, 0, 0, 2, (0, 0), Z)), Schedule(T, w.so // 2, 0, 2, (0, 0), Z))
+                    for Z in (32, 48, 64))
+            row["skewed"] = _row("skewed", r[0], r[1])
+        rows.append(row)
+        log("depth %d: register-tiled %s, skewed %s" % (T, row["register_tiled"].get("value"),
+                                                        row.get("skewed", {}).get("value")))
+    return rows
+
+
+def c3_bench(dev, stream, quick=False):
+    """768^3 (+40 = 848^3), smooth random model, space orders 12 and 16, 500
+    steps: the autotuned schedule, the untiled sweep and the best time-tiled
+    schedule (register-tiled or skewed), each over the full run."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import WaveOp
+    from paper_1806_08299_amd.wave import Schedule, tile_table, wave_scratch_bytes, wave_tiled_max_depth
+    n, nt = (160, 60) if quick else (768, 500)
+    t0 = time.time()
+    base = wi.smooth_768(so=12, nt=nt, n=n, device=dev)
+    log("smooth_768 model generated in %.1f s" % (time.time() - t0))
+    m = torch.from_numpy(base.m).to(dev)
+    out = []
+    for so in (12, 16):
+        w = wi.Workload("smooth_%dcube_so%d" % (n, so), base.shape, base.spacing, base.dt, so, nt, base.nbl,
+                        base.sigma_max, base.m, base.src_xyz, base.wavelet, base.rec_xyz)
+        wav = torch.from_numpy(w.wavelet).to(dev)
+        op = WaveOp(w.shape, w.spacing, w.dt, so, m, nbl=w.nbl, sigma_max=w.sigma_max, time_tile=-1)
+        from paper_1806_08299_amd.wave import wave_autotune
+        sc = op.scratch(wave_scratch_bytes(op.ctx, 16, 0, 0, 0, 0))
+        wave_autotune(op.ctx, 16, 1, 8, sc)
+        op._scratch = None
+        tuned = op.schedule()
+        v_t = _rate(op, nt, w, wav, stream, 1)
+        untiled = max((_rate(op, nt, w, wav, stream, 1, Schedule(-1, 0, 0, zc, (0, 0), 0)), zc) for zc in (0, 24))
+        cands = [Schedule(T, 0, i + 1, 16, t, 0) for i, t in enumerate(tile_table(3))
+                 for T in range(1, wave_tiled_max_depth(so, 3, tile=t) + 1)]
+        cands += [Schedule(T, 0, 0, 2, (0, 0), Z) for T in (4, 8) for Z in (48, 64)]
+        if tuned[0] >= 1:
+            cands = [tuned]
+        best = max((_rate(op, nt, w, wav, stream, 1, c), c) for c in cands)
+        row = {"workload": w.name, "shape": list(w.shape), "space_order": so, "nt": nt, "unit": "Gpts/s",
+               "autotuned": _row("autotuned", v_t, tuned),
+               "untiled": _row("untiled", untiled[0], Schedule(-1, so // 2, 0, untiled[1], (0, 0), 0)),
+               "best_time_tiled": _row("time-tiled", best[0], best[1]),
+               "speedup_vs_untiled": round(max(v_t, best[0]) / untiled[0], 3)}
+        out.append(row)
+        log("smooth so%d: autotuned %s %.1f, untiled %.1f, best tiled %.1f %s" % (so, tuned, v_t, untiled[0],
+                                                                              best[0], best[1]))
+        del op
+        torch.cuda.empty_cache()
+    del m, base
+    torch.cuda.empty_cache()
+    return out
+
+
+def wave2d_bench(dev, stream, quick=False):
+    """2D 16384^2 (16384 x 16384 points, layered model, 40-point layer
+    inside), space orders 2, 4, 8, 100 steps: the untiled sweep against the
+    best register-tiled (1 x 1024 tiles, depth up to the built limit) and
+    skewed schedules."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import WaveOp
+    from paper_1806_08299_amd.wave import Schedule, wave_tiled_max_depth
+    n, nt = (2048, 50) if quick else (16384, 100)
+    shape = (n - 80, n - 80)
+    c = wi.layered_velocity(shape, 8, seed=7)
+    out = []
+    for so in (2, 4, 8):
+        w = wi.make_workload("layered2d_%d_so%d" % (n, so), shape, 10.0, so, nt, 40, c, 10.0, (20, shape[1] // 2),
+                             2, c_max=wi.C_MAX)
+        wav = torch.from_numpy(w.wavelet).to(dev)
+        op = WaveOp(w.shape, w.spacing, w.dt, so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
+                    sigma_max=w.sigma_max, time_tile=-1)
+        u = max((_rate(op, nt, w, wav, stream, 2, Schedule(-1, 0, 0, zc, (0, 0), 0)), zc) for zc in (0, 64, 256))
+        reg = max((_rate(op, nt, w, wav, stream, 2, Schedule(T, 0, 0, zc, (1, 1024), 0)), Schedule(T, so // 2, 1, zc, (1, 1024), 0))
+                  for T in range(1, wave_tiled_max_depth(so, 2) + 1) for zc in (0, 64, 256))
+        skw = max((_rate(op, nt, w, wav, stream, 2, Schedule(T, 0, 0, zc, (0, 0), Z)), Schedule(T, so // 2, 0, zc, (0, 0), Z))
+                  for T in (4, 8) for Z in (512, 1024) for zc in (0, 8))
+        out.append({"workload": w.name, "shape": list(w.shape), "space_order": so, "nt": nt, "unit": "Gpts/s",
+                    "untiled": _row("untiled", u[0], Schedule(-1, so // 2, 0, u[1], (0, 0), 0)),
+                    "register_tiled": _row("register-tiled", reg[0], reg[1]),
+                    "skewed": _row("skewed", skw[0], skw[1]),
+                    "speedup_vs_untiled": round(max(reg[0], skw[0]) / u[0], 3)})
+        log("2D so%d: untiled %.1f, register-tiled %.1f %s, skewed %.1f %s" % (so, u[0], reg[0], reg[1], skw[0], skw[1]))
+        del op
+        torch.cuda.empty_cache()
+    return out
+
+
+def tiling_factor(so, dev, stream, nt=100, n=512):
+    """Best untiled and best time-tiled schedule (register-tiled over every
+    built tile and depth, or skewed) for the layered workload at space order
+    `so` (short runs, minimum of 2), and their ratio."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import WaveOp
+    from paper_1806_08299_amd.wave import Schedule, tile_table, wave_tiled_max_depth
     w = wi.layered_512(nt=nt, n=n, so=so)
     op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
                 sigma_max=w.sigma_max, time_tile=-1)
     wav = torch.from_numpy(w.wavelet).to(dev)
-
-    def rate(sched):
-        try:
-            op.set_schedule(*sched)
-        except WaveError:
-            return 0.0
-        op.forward(nt, w.src_xyz, wav, w.rec_xyz)
-        t, _ = run_steps(op, w, wav, 1, stream)
-        t = min(t, run_steps(op, w, wav, 1, stream)[0])
-        return w.npts * nt / t / 1e9
-
-    untiled = max((rate((-1, 0, 1, zc)), zc) for zc in (12, 16, 24))
-    tiled = max((rate((T, 0, shape, zc)), (T, shape, zc)) for shape in (1, 2)
-                for T in range(1, wave_tiled_max_depth(so, 3, shape) + 1) for zc in (0, 16, 32))
+    untiled = max((_rate(op, nt, w, wav, stream, 2, Schedule(-1, 0, 0, zc, (0, 0), 0)), zc) for zc in (12, 16, 24))
+    cands = [Schedule(T, 0, i + 1, zc, t, 0) for i, t in enumerate(tile_table(3))
+             for T in range(1, wave_tiled_max_depth(so, 3, tile=t) + 1) for zc in (0, 16, 32)]
+    cands += [Schedule(T, 0, 0, 2, (0, 0), Z) for T in (4, 8) for Z in (48, 64)]
+    tiled = max((_rate(op, nt, w, wav, stream, 2, c), c) for c in cands)
     del op
     torch.cuda.empty_cache()
     return {"space_order": so, "untiled": round(untiled[0], 1), "untiled_zchunks": untiled[1],
-            "tiled": round(tiled[0], 1), "tiled_schedule": dict(zip(("T", "tile_shape", "zchunks"), tiled[1])),
+            "tiled": round(tiled[0], 1), "tiled_schedule": sched_dict(tiled[1]),
             "factor": round(tiled[0] / untiled[0], 3)}
 
 
@@ -397,7 +683,8 @@ def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16
 
             def rate(sched):
                 try:
-                    op.set_schedule(*sched)
+                    op.set_schedule(*sched[:4], tile=sched[4] if len(sched) > 4 else None,
+                                    slab=sched[5] if len(sched) > 5 else 0)
                 except WaveError:
                     return 0.0
                 op.forward(nt, u0, res)
@@ -412,23 +699,24 @@ def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16
                     ts.append(e0.elapsed_time(e1) * 1e-3)
                 return w.npts * nt / min(ts) / 1e9
 
-            d_rate = rate((dflt[0], dflt[1], dflt[2], dflt[3]))
+            d_rate = rate(tuple(dflt))
             untiled = max((rate((-1, 0, 0, zc)), zc) for zc in (0, 8, 24))
-            cands = [(T, shape, zc) for shape in (2, 1) for T in range(1, min(4, wave_tiled_max_depth(so, 3, shape)) + 1)
-                     for zc in (0, 4, 8, 16)]
-            tiled = max((rate((T, 0, shape, zc)), (T, shape, zc)) for T, shape, zc in cands)
+            cands = [(T, shape, zc, 0) for shape in (2, 1, 3, 4)
+                     for T in range(1, min(4, wave_tiled_max_depth(so, 3, shape)) + 1) for zc in (0, 4, 8, 16)]
+            cands += [(T, 0, 2, Z) for T in (4, 8) for Z in (32, 64)]
+            tiled = max((rate((T, 0, shape, zc, None, Z)), (T, shape, zc, Z)) for T, shape, zc, Z in cands)
             Tb = tiled[1][0]
 
             def gbs(v, T):
                 return v * 1e9 * wave_bytes_per_point(T, 3) / 1e9
             out.append({"workload": w.name, "nt": nt, "space_order": so,
-                        "default_schedule": dict(zip(("T", "skew", "tile_shape", "zchunks"), dflt)),
+                        "default_schedule": sched_dict(dflt),
                         "default": round(d_rate, 1),
                         "untiled": round(untiled[0], 1), "untiled_zchunks": untiled[1],
                         "untiled_GBs": round(gbs(untiled[0], -1), 1),
                         "untiled_frac": round(gbs(untiled[0], -1) / HBM_PEAK_GBS, 4),
                         "tiled": round(tiled[0], 1),
-                        "tiled_schedule": dict(zip(("T", "tile_shape", "zchunks"), tiled[1])),
+                        "tiled_schedule": dict(zip(("T", "tile_shape", "zchunks", "slab"), tiled[1])),
                         "tiled_GBs": round(gbs(tiled[0], Tb), 1),
                         "tiled_frac": round(gbs(tiled[0], Tb) / HBM_PEAK_GBS, 4),
                         "factor": round(tiled[0] / untiled[0], 3)})
@@ -441,6 +729,65 @@ def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16
     return out
 
 
+def ab2_bench(dev, stream, n=500, nt=32, orders=(2, 4, 8), quick=False):
+    """The two-level (delta_t = 2) Laplace-operator stencil, the two-step
+    Adams-Bashforth rule, on the 500^3 x 32-step grid of the Laplace section:
+    the untiled sweep (12 B per point-update: two levels read, one written)
+    against the best skewed schedule (16/T B), beside the one-level step's
+    untiled and skewed rates on the same grid: the paper's hypothesis that
+    time-tiling gains more with a larger time dependence."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import DiffOp, WaveError
+    from paper_1806_08299_amd.wave import wave_bytes_per_point
+    if quick:
+        n = 128
+    base = wi.laplace(n=n, so=orders[0], nt=nt)
+    u0 = torch.from_numpy(base.u0).to(dev)
+    res = torch.empty_like(u0)
+    out = []
+    for so in orders:
+        rows = {}
+        for scheme, mode, dt in (("ab2", 4, base.dt / 2.0), ("euler", 3, base.dt / 2.0)):
+            op = DiffOp(base.shape, base.spacing, dt, base.alpha, so, time_tile=-1, scheme=scheme)
+
+            def rate(T, Z, zc):
+                try:
+                    op.set_schedule(T, 0, 0, zc, slab=Z)
+                except WaveError:
+                    return 0.0
+                op.forward(nt, u0, res)
+                ts = []
+                for _ in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    torch.cuda.synchronize()
+                    e0.record(stream)
+                    op.forward(nt, u0, res)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    ts.append(e0.elapsed_time(e1) * 1e-3)
+                return base.npts * nt / min(ts) / 1e9
+
+            u = max((rate(-1, 0, zc), zc) for zc in (0, 8, 24))
+            sk = max((rate(T, Z, zc), (T, Z, zc)) for T in (4, 8, 16) for Z in (32, 48, 64) for zc in (2,))
+            bu, bs = wave_bytes_per_point(-1, mode), wave_bytes_per_point(sk[1][0], mode)
+            rows[scheme] = {"untiled": round(u[0], 1), "untiled_GBs": round(u[0] * bu, 1),
+                            "untiled_frac": round(u[0] * bu / HBM_PEAK_GBS, 4),
+                            "skewed": round(sk[0], 1), "skewed_schedule": dict(zip(("T", "slab", "zchunks"), sk[1])),
+                            "skewed_GBs": round(sk[0] * bs, 1), "skewed_frac": round(sk[0] * bs / HBM_PEAK_GBS, 4),
+                            "factor": round(sk[0] / u[0], 3)}
+            del op
+            torch.cuda.empty_cache()
+        out.append({"workload": "laplace_%dcube_so%d, %d steps, dt at 0.9 of the two-level limit" % (n, so, nt),
+                    "space_order": so, "unit": "Gpts/s", "two_level": rows["ab2"], "one_level_same_dt": rows["euler"]})
+        log("ab2 so%d: untiled %.1f, skewed %.1f (%.3fx); one-level %.1f / %.1f (%.3fx)"
+            % (so, rows["ab2"]["untiled"], rows["ab2"]["skewed"], rows["ab2"]["factor"],
+               rows["euler"]["untiled"], rows["euler"]["skewed"], rows["euler"]["factor"]))
+    del u0, res, base
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -450,7 +797,8 @@ def main():
     ap.add_argument("--nt", type=int, default=1000)
     ap.add_argument("--so", type=int, default=8, help="space order of the forward workload")
     ap.add_argument("--T", type=int, default=0, help="time-tile depth (0: autotune, -1: untiled)")
-    ap.add_argument("--shape", type=int, default=1)
+    ap.add_argument("--shape", type=int, default=1, help="register-tiled: index of the extended tile")
+    ap.add_argument("--slab", type=int, default=0, help="skewed schedule: slab thickness (0: not skewed)")
     ap.add_argument("--zchunks", type=int, default=0)
     ap.add_argument("--no-untiled", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
@@ -458,6 +806,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-orders", action="store_true")
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-operator (diffusion) section")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 64^3 point-source section")
+    ap.add_argument("--no-depths", action="store_true", help="skip the depth sweep of the headline workload")
+    ap.add_argument("--no-smooth", action="store_true", help="skip the 768^3 smooth-model section")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D section")
+    ap.add_argument("--no-ab2", action="store_true", help="skip the two-level (Adams-Bashforth) section")
     ap.add_argument("--laplace-only", action="store_true",
                     help="diagnostic: run only the Laplace-operator section and print its results")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -503,7 +856,7 @@ def main():
         del x
         log("copy calibration: 12 copies of %d bytes" % (w.npts * 4))
     if args.T != 0:
-        op.set_schedule(args.T, 0, args.shape, args.zchunks)
+        op.set_schedule(args.T, 0, args.shape if args.slab == 0 else 0, args.zchunks, slab=args.slab)
     else:
         best = autotune(op)
         log("autotune -> schedule %s, %.3f ms/step" % (op.schedule(), best * 1e3))
@@ -560,14 +913,18 @@ def main():
     del s3
 
     # ---------------------------------------------------------------- roofline of the dominant kernel
-    # One step = ceil(nt / T) launches of the sweep kernel plus four small
-    # kernels (forcing table, two fills, receiver reduction; < 0.1 % of the
-    # step), so the kernel's average launch time is bounded by step / launches.
+    # One step = the sweep launches of the schedule (ceil(nt / T) register-
+    # tiled or untiled launches over the grid, or one launch per slab and
+    # step of the skewed schedule) plus four small kernels (forcing table,
+    # two fills, receiver reduction; < 0.1 % of the step).  Algorithmic bytes
+    # of the step: bytes per point-update of the schedule x points x nt; per
+    # launch: that over the launches (every launch of a skewed step moves one
+    # slab's share).
     Tn = max(T, 1)
-    launches = -(-w.nt // Tn)
+    launches = launches_per_step(sched, w.shape[0], w.nt)
     t_launch = t_step / launches
     bpp = wave_bytes_per_point(T, 0)
-    alg_bytes = bpp * w.npts * Tn                   # per launch (full window)
+    alg_bytes = bpp * w.npts * w.nt / launches      # per launch, on average
     achieved = alg_bytes / t_launch / 1e9
     flops_pt = wave_flops_per_point(3, w.so, 0)
     rec = traffic_record(w.name, sched)
@@ -580,7 +937,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "kernel": kernel_name(sched, w.so), "algorithmic_bytes_per_launch": alg_bytes,
-                "bytes_per_point_update": bpp, "points_per_launch": w.npts * Tn,
+                "bytes_per_point_update": bpp, "point_updates_per_launch": round(w.npts * w.nt / launches),
                 "avg_launch_ms": round(t_launch * 1e3, 4), "launches_per_step": launches,
                 "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "stream_3r1w_GBs": round(stream_gbs, 1), "frac_of_stream_3r1w": round(achieved / stream_gbs, 4)}
@@ -592,17 +949,25 @@ def main():
     ai_s = flops_pt / 16.0
     ai = {"flops_per_point_update": flops_pt, "untiled_ai": round(ai_s, 4),
           "naive": round(wave_ai_naive(ai_s, Tn), 4)}
-    from paper_1806_08299_amd.wave import block_extent
-    # tile sizes: the extended tile of the tiled sweep, the 16 x 64 block of the untiled one
-    ey, ex = block_extent(3, sched[2]) if T >= 1 else (16, 64)
+    # tile sizes: the extended tile of the register-tiled sweep, the 16 x 64
+    # block of the single-step kernel (untiled or skewed; the skewed slab is
+    # the tile along axis 0)
+    ey, ex = tuple(sched[4]) if (T >= 1 and sched[5] == 0) else (16, 64)
+    t0_ = sched[5] if sched[5] > 0 else w.shape[0]
     for nm, om in (("tight_l2", L2_FLOATS), ("tight_mall", MALL_FLOATS)):
-        ai[nm] = round(wave_ai_tight(ai_s, Tn, w.shape, [w.so // 2] * 3, [w.shape[0], ey, ex], om), 4)
+        ai[nm] = round(wave_ai_tight(ai_s, Tn, w.shape, [w.so // 2] * 3, [t0_, ey, ex], om), 4)
     if traffic:
-        ai["measured"] = round(flops_pt * w.npts * Tn / traffic, 4)
+        ai["measured"] = round(flops_pt * w.npts * w.nt / launches / traffic, 4)
     ai["compulsory"] = round(flops_pt / bpp, 4)
+    depths = None
+    if not args.no_depths:
+        depths = depth_sweep(op, w, wav, stream, nt=20 if args.quick else 40)
     del op, m, wav
     torch.cuda.empty_cache()
 
+    c1 = None if args.no_c1 else c1_bench(dev, stream)
+    c3 = None if args.no_smooth else c3_bench(dev, stream, quick=args.quick)
+    w2d = None if args.no_2d else wave2d_bench(dev, stream, quick=args.quick)
     adj = None if args.no_adjoint else gradient_bench(args, dev, stream)
     batch = None if args.no_batch else batch_bench(args, dev, stream)
     orders = None
@@ -615,7 +980,8 @@ def main():
     lap = None
     if not args.no_laplace:
         lap = laplace_bench(dev, stream, grids=((128, 32),) if args.quick else ((500, 32), (600, 16)))
-    cpu = None if args.no_cpu else cpu_baseline(w, n=args.n)
+    ab2 = None if args.no_ab2 else ab2_bench(dev, stream, quick=args.quick)
+    cpu = None if args.no_cpu else cpu_baseline(w, n=args.n, quick=args.quick)
 
     line = {
         "metric": "Gpts/s fwd & adjoint-grad vs untiled sweep; % HBM roofline (1 MI355X)",
@@ -624,13 +990,18 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "shape": list(w.shape), "physical": [args.n] * 3, "nbl": w.nbl,
                    "space_order": w.so, "nt": w.nt,
-                   "schedule": dict(zip(("T", "skew", "tile_shape", "zchunks"), sched))},
+                   "schedule": sched_dict(sched)},
         "untiled": untiled,
         "speedup_vs_untiled": round(value / untiled["value"], 3) if untiled else None,
         "adjoint_grad": adj,
         "batch": batch,
         "tiling_by_order": orders,
+        "depth_sweep": depths,
+        "point_source_64": c1,
+        "smooth_768": c3,
+        "wave2d": w2d,
         "laplace": lap,
+        "two_level_laplace": ab2,
         "roofline": roofline,
         "ai": ai,
         "cpu_baseline": cpu,

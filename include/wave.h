@@ -292,16 +292,28 @@ typedef struct diff_desc {
   int32_t slab;          /* as in wave_desc */
   int32_t zchunks;       /* as in wave_desc; 0 = auto (time-tiled: about 6 workgroups per CU
                             in 3D, 16 in 2D) */
+  int32_t scheme;        /* 0: one time level, u^{n+1} = u^n + dt a L u^n (forward Euler);
+                            1: two time levels (delta_t = 2; evaluation chapter, "Time-tiling
+                            with larger time dependences"), the two-step Adams-Bashforth
+                            rule u^{n+1} = u^n + dt a (3/2 L u^n - 1/2 L u^{n-1}) with
+                            u^{-1} = u^0.  Scheme 1 runs the untiled sweep or the skewed
+                            schedule (slab > 0; WAVE_EUNSUPPORTED for register tiles); its
+                            default (time_tile = 0) is skewed, T = 8 on slabs of 48 planes,
+                            up to radius 2 in 3D, untiled otherwise; its stability limit
+                            is half that of scheme 0 */
 } diff_desc;
 
-/* Flops per point-update of explicit diffusion (FMA = 2). Host-only. */
-double diff_flops_per_point(int32_t ndim, int32_t space_order);
+/* Flops per point-update of explicit diffusion (FMA = 2) for scheme 0 (one
+ * level) or 1 (two levels: also forming 3/2 u^n - 1/2 u^{n-1}). Host-only. */
+double diff_flops_per_point(int32_t ndim, int32_t space_order, int32_t scheme);
 
-/* Bytes of device state for `d`: two levels of N floats (0 if d is invalid). */
+/* Bytes of device state for `d`: two levels of N floats (scheme 1: three)
+ * (0 if d is invalid). */
 size_t diff_state_bytes(const diff_desc* d);
 
-/* Validate `d` (as wave_desc, plus alpha > 0 finite) and the stability limit
- * dt a sum_a rho / h_a^2 <= 2 (rho as for wave_init), and carve the state.
+/* Validate `d` (as wave_desc, plus alpha > 0 finite, scheme 0 or 1) and the
+ * stability limit dt a sum_a rho / h_a^2 <= 2 (scheme 1: <= 1; rho as for
+ * wave_init), and carve the state.
  * The context takes wave_set_schedule, wave_get_schedule, wave_autotune,
  * wave_scratch_bytes, wave_last_error and wave_destroy; the wave-equation
  * calls reject it with WAVE_ESTATE.

@@ -33,6 +33,7 @@ def sources():
     srcs = [os.path.join(CSRC, "wave_api.cpp")]
     srcs += [os.path.join(CSRC, "wave_r%d_%s%d.hip" % (r, k, m)) for r in range(1, 9) for k in "mb" for m in range(3)]
     srcs += [os.path.join(CSRC, "wave_r%d_m3.hip" % r) for r in range(1, 9)]   # explicit diffusion
+    srcs += [os.path.join(CSRC, "wave_r%d_m4.hip" % r) for r in range(1, 9)]   # two-level diffusion
     return srcs
 
 

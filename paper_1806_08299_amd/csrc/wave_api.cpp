@@ -50,7 +50,8 @@ struct BatchGraph {
 
 struct wave_ctx {
   wave_desc d;
-  int eq = 0;                    // 0: wave equation (wave_init); 1: explicit diffusion (diff_init)
+  int eq = 0;                    // 0: wave equation (wave_init); 1: explicit diffusion, 2: its
+                                 // two-level Adams-Bashforth form (diff_init)
   int R = 0;
   int dim = 3;
   int64_t n0 = 1, n1 = 1, n2 = 1, N = 0;
@@ -492,6 +493,7 @@ wave_status launch_window(wave_ctx* c, const Plan& p, SweepArgs A) {
   dim3 grid((unsigned)A.nblocks);
   int mode = MODE_FWD;
   if (c->eq == 1) mode = MODE_DIFF;
+  else if (c->eq == 2) mode = MODE_AB2;
   else if (A.grad) mode = MODE_ADJ;
   else if (A.hist) mode = MODE_HIST;
   if (c->rec) {
@@ -792,13 +794,14 @@ int tiled_tmax(int R, int dim, int shape) {
 
 hipError_t launch_sweep(int R, int kind, int T, int dim, int mode, int shape, const SweepArgs& A, dim3 grid,
                         size_t lds, hipStream_t s) {
-  if (mode < 0 || mode > 3) return hipErrorInvalidValue;
+  if (mode < 0 || mode > 4) return hipErrorInvalidValue;
 #define WAVE_CASE(RR)                                                                  \
   case RR:                                                                             \
     return mode == 0 ? launch_sweep_r##RR##_m0(kind, T, dim, shape, A, grid, lds, s)  \
          : mode == 1 ? launch_sweep_r##RR##_m1(kind, T, dim, shape, A, grid, lds, s)  \
          : mode == 2 ? launch_sweep_r##RR##_m2(kind, T, dim, shape, A, grid, lds, s)  \
-                     : launch_sweep_r##RR##_m3(kind, T, dim, shape, A, grid, lds, s);
+         : mode == 3 ? launch_sweep_r##RR##_m3(kind, T, dim, shape, A, grid, lds, s)  \
+                     : launch_sweep_r##RR##_m4(kind, T, dim, shape, A, grid, lds, s);
   switch (R) {
     WAVE_CASE(1) WAVE_CASE(2) WAVE_CASE(3) WAVE_CASE(4) WAVE_CASE(5) WAVE_CASE(6) WAVE_CASE(7) WAVE_CASE(8)
     default: return hipErrorInvalidValue;
@@ -859,6 +862,8 @@ static wave_status apply_schedule(wave_ctx* c, int T, int skew, int shape, int s
     return fail(c, WAVE_EINVAL, "bad schedule");
   if (slab == 0 && T > 8) return fail(c, WAVE_EUNSUPPORTED, "register-tiled depth above 8");
   if (slab > 0 && T < 1) return fail(c, WAVE_EINVAL, "the skewed schedule needs a depth T >= 1");
+  if (c->eq == 2 && T >= 1 && slab == 0)
+    return fail(c, WAVE_EUNSUPPORTED, "the two-level step runs untiled or skewed (slab > 0) only");
   c->T = T;
   c->skew = skew ? skew : c->R;
   c->shape = (c->dim == 3) ? (shape ? shape : 1) : 0;
@@ -1073,7 +1078,7 @@ void wave_destroy(wave_ctx* c) {
 
 size_t wave_scratch_bytes(const wave_ctx* c, int32_t nt, int32_t nsrc, int32_t nrec, int32_t K, int32_t adjoint) {
   if (!c || nt < 0 || nsrc < 0 || nrec < 0 || K < 0) return 0;
-  if (c->eq == 1) return 2 * align_up(sizeof(float) * c->N);   // diffusion: wave_autotune's two levels
+  if (c->eq != 0) return 2 * align_up(sizeof(float) * c->N);   // diffusion: wave_autotune's two levels
   return layout(c, nt, nsrc, nrec, K, adjoint).total;
 }
 
@@ -1443,7 +1448,7 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
   // Wave equation: trial forwards with the scratch layout of wave_forward.
   // Diffusion: trial diff_forward calls from a zero field in the first half
   // of the scratch into its second half.
-  const bool diff = c->eq == 1;
+  const bool diff = c->eq != 0;
   const Layout L = diff ? Layout{} : layout(c, trial_steps, 0, 0, 0, 0);
   const size_t level = align_up(sizeof(float) * c->N);
   if (!scratch || scratch_bytes < (diff ? 2 * level : L.total)) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
@@ -1617,16 +1622,18 @@ double wave_bytes_per_point(int32_t T, int32_t mode) {
   // at every stage of the window).
   const double Tt = T < 1 ? 1.0 : (double)T;
   if (mode == 3) return 8.0 / Tt;   // diffusion: read u^n, write u^{n+T}
+  if (mode == 4) return T <= 1 ? 12.0 : 16.0 / Tt;   // two-level: read 2 levels, write 1 (2 per time tile)
   double base = (T <= 1) ? 16.0 : 20.0 / Tt;
   if (mode == 1) base += 4.0;
   if (mode == 2) base += 4.0 + 8.0;
   return base;
 }
 
-double diff_flops_per_point(int32_t ndim, int32_t so) {
-  // centre product, per axis per pair one add + one FMA, the final add
+double diff_flops_per_point(int32_t ndim, int32_t so, int32_t scheme) {
+  // centre product, per axis per pair one add + one FMA, the final add; the
+  // two-level step also forms 3/2 u^n - 1/2 u^{n-1} (a multiply and an FMA)
   const double r = so / 2;
-  return 2.0 + 3.0 * ndim * r;
+  return 2.0 + 3.0 * ndim * r + (scheme == 1 ? 3.0 : 0.0);
 }
 
 // ====================================================== explicit diffusion
@@ -1655,8 +1662,10 @@ static wave_desc diff_as_wave(const diff_desc* d) {
   return w;
 }
 
-// Von Neumann limit of explicit diffusion: dt a sum_a rho / h_a^2 <= 2, with
-// rho the magnitude of the weights' symbol at the Nyquist wavenumber.
+// Stability limit of explicit diffusion: dt a sum_a rho / h_a^2 <= 2 for the
+// forward-Euler step, <= 1 for the two-step Adams-Bashforth rule (its region
+// on the negative real axis is [-1, 0]), with rho the magnitude of the
+// weights' symbol at the Nyquist wavenumber.  Returns the ratio to the limit.
 static double diff_stability(const diff_desc* d) {
   double c[9];
   fd_weights(d->space_order, c);
@@ -1664,16 +1673,26 @@ static double diff_stability(const diff_desc* d) {
   for (int j = 1; j <= d->space_order / 2; ++j) rho -= 2.0 * c[j] * ((j & 1) ? -1.0 : 1.0);
   double s = 0.0;
   for (int a = 0; a < d->ndim; ++a) s += rho / (d->spacing[a] * d->spacing[a]);
-  return d->dt * d->alpha * s / 2.0;
+  return d->dt * d->alpha * s / (d->scheme == 1 ? 1.0 : 2.0);
 }
 
+// Levels of state: the one-level step ping-pongs two, the two-level step
+// rotates three (the new level overwrites the one two steps back).
+static int diff_levels(const diff_desc* d) { return d->scheme == 1 ? 3 : 2; }
+
+// Default skewed schedule of the two-level step (0: untiled), from
+// measurements on MI355X.
+static int ab2_default_depth(const wave_ctx* c) { return (c->dim == 3 && c->R <= 2) ? 8 : 0; }
+static int ab2_default_slab(const wave_ctx* c) { (void)c; return 48; }
+
+
 size_t diff_state_bytes(const diff_desc* d) {
-  if (!d) return 0;
+  if (!d || d->scheme < 0 || d->scheme > 1) return 0;
   const wave_desc w = diff_as_wave(d);
   std::string msg;
   wave_status s = check_desc(&w, msg);
   if (s != WAVE_OK && s != WAVE_ESKEW) return 0;
-  return 2 * align_up(sizeof(float) * npts_of(&w));
+  return diff_levels(d) * align_up(sizeof(float) * npts_of(&w));
 }
 
 wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void* stream, wave_ctx** out) {
@@ -1685,13 +1704,14 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
   wave_status s = check_desc(&w, msg);
   if (s != WAVE_OK) return s;
   if (!(d->alpha > 0.0) || !std::isfinite(d->alpha)) return WAVE_EINVAL;
+  if (d->scheme < 0 || d->scheme > 1) return WAVE_EINVAL;
   if (diff_stability(d) > 1.0 + 1e-12) return WAVE_ECFL;
   if (!state) return WAVE_EINVAL;
   if (state_bytes < diff_state_bytes(d)) return WAVE_ENOMEM;
   static std::atomic<uint64_t> next_id{1u << 30};
   wave_ctx* c = new wave_ctx();
   c->id = ++next_id;
-  c->eq = 1;
+  c->eq = d->scheme == 1 ? 2 : 1;
   c->d = w;
   c->R = d->space_order / 2;
   c->dim = d->ndim;
@@ -1721,11 +1741,16 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
     c->C.w[2][j - 1] = (float)(cw[j] * kx);
   }
   char* p = (char*)state;
-  c->w[0] = (float*)p;
-  c->w[1] = (float*)(p + align_up(sizeof(float) * c->N));
+  for (int i = 0; i < diff_levels(d); ++i) c->w[i] = (float*)(p + i * align_up(sizeof(float) * c->N));
   const int shape0 = tile_index(d->ndim, d->tile[0], d->tile[1]);
   s = apply_schedule(c, d->time_tile == 0 ? -1 : d->time_tile, d->skew, shape0,
                      d->time_tile == 0 ? 0 : d->slab, d->zchunks);
+  if (s == WAVE_OK && c->eq == 2 && d->time_tile == 0) {
+    // two-level step: the skewed schedule by default where it measured
+    // faster than the untiled sweep on MI355X (see diff_desc)
+    const int Ta = ab2_default_depth(c), Za = ab2_default_slab(c);
+    if (Ta > 0) s = apply_schedule(c, Ta, 0, 0, Za, 0);
+  }
   if (s != WAVE_OK) {
     delete c;
     return s;
@@ -1738,7 +1763,7 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
   int Td = 0;
   if (c->dim == 3) Td = c->R == 1 ? 4 : (c->R == 2 ? 2 : (c->R <= 4 ? 1 : 0));
   else Td = c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0);
-  if (d->time_tile == 0 && Td > 0) {
+  if (d->time_tile == 0 && Td > 0 && c->eq == 1) {
     const int oshape = c->shape;
     if (c->dim == 3 && shape0 == 0) c->shape = 2;
     Plan pl;
@@ -1750,10 +1775,59 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
   return WAVE_OK;
 }
 
+// The two-level step, nt >= 1 steps.  Level l lives in u0 (l = 0, and
+// l = -1: u^{-1} = u^0), u_out (l = nt) or state level (l - 1) % 3; the
+// launch producing level l + 1 reads levels l and l - 1 (both through the
+// stencil) and overwrites level l - 2.  Skewed (slab > 0): level l - 2's last
+// readers are step l - 1 (as its t - 1 level) and step l (as its t - 2
+// level) of later slabs, from planes (j+1)Z - (k-1)s - r on, beyond what
+// slab j's step k writes ((j+1)Z - ks) since s >= r.
+static wave_status ab2_forward(wave_ctx* c, int nt, const float* u0, float* u_out) {
+  auto buf = [&](int l) -> float* { return l <= 0 ? (float*)u0 : (l == nt ? u_out : c->w[(l - 1) % 3]); };
+  auto launch = [&](int l, int64_t lo, int64_t hi) -> wave_status {
+    Plan p;
+    wave_status s = make_plan(c, KIND_UNTILED, 1, p, lo, hi);
+    if (s != WAVE_OK) return s;
+    SweepArgs A = base_args(c);
+    A.cur = buf(l);
+    A.prev = buf(l - 1);
+    A.b = A.cur;   // not read in this mode
+    A.outA = buf(l + 1);
+    A.outB = nullptr;
+    A.step0 = l;
+    A.dir = 1;
+    return launch_window(c, p, A);
+  };
+  if (!(c->T >= 1 && c->slab > 0)) {
+    for (int l = 0; l < nt; ++l) {
+      wave_status s = launch(l, 0, c->n0);
+      if (s != WAVE_OK) return s;
+    }
+    return WAVE_OK;
+  }
+  const int64_t sk = c->skew, Z = c->slab;
+  int done = 0;
+  while (done < nt) {
+    const int Tw = std::min(c->T, nt - done);
+    const int64_t J = (c->n0 + (int64_t)(Tw - 1) * sk + Z - 1) / Z;
+    for (int64_t j = 0; j < J; ++j) {
+      for (int k = 0; k < Tw; ++k) {
+        const int64_t lo = std::max<int64_t>(0, j * Z - k * sk);
+        const int64_t hi = std::min<int64_t>(c->n0, (j + 1) * Z - k * sk);
+        if (lo >= hi) continue;
+        wave_status s = launch(done + k, lo, hi);
+        if (s != WAVE_OK) return s;
+      }
+    }
+    done += Tw;
+  }
+  return WAVE_OK;
+}
+
 wave_status diff_forward(wave_ctx* c, int32_t nt, const float* u0, float* u_out) {
   if (!c) return WAVE_EINVAL;
   c->err.clear();
-  if (c->eq != 1) return fail(c, WAVE_ESTATE, "not a diffusion context");
+  if (c->eq != 1 && c->eq != 2) return fail(c, WAVE_ESTATE, "not a diffusion context");
   if (nt < 0) return fail(c, WAVE_EINVAL, "negative nt");
   if (!u0 || !u_out) return fail(c, WAVE_EINVAL, "null field");
   // One launch reads its input while other workgroups write its output, so
@@ -1765,10 +1839,11 @@ wave_status diff_forward(wave_ctx* c, int32_t nt, const float* u0, float* u_out)
     return a < b + n && b < a + n;
   };
   if (overlap(u0, u_out)) return fail(c, WAVE_EINVAL, "u_out must not overlap u0");
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < (c->eq == 2 ? 3 : 2); ++i)
     if (overlap(u0, c->w[i]) || overlap(u_out, c->w[i]))
       return fail(c, WAVE_EINVAL, "u0 and u_out must not overlap the context's state");
   if (nt == 0) return copy(c, u0, u_out, c->N);
+  if (c->eq == 2) return ab2_forward(c, nt, u0, u_out);
   if (c->T >= 1 && c->slab > 0) {
     // The skewed schedule (see run_steps_skewed).  Level l lives in u0
     // (l = 0), u_out (l = nt) or state level (l - 1) % 2: level l + 1

@@ -81,6 +81,32 @@ __device__ __forceinline__ float diff_next(const Coefs& C, float uc,
   return uc + lap;
 }
 
+// The two-level (Adams-Bashforth) diffusion step.  The rule
+// u + dt a (3/2 L u^n - 1/2 L u^{n-1}) equals u + dt a L w with
+// w = 3/2 u^n - 1/2 u^{n-1} (L is linear), so the sweeps stream w through
+// the windows and planes the one-level step streams u through: ab2_input
+// forms w once per loaded point (one rounding: -u^{n-1}/2 is exact), and
+// ab2_next adds the scaled Laplacian of w to u^n.  Same operation order in
+// every schedule.
+__device__ __forceinline__ float ab2_input(float un, float unm1) { return __builtin_fmaf(1.5f, un, -0.5f * unm1); }
+
+template <int R, bool HAS_Y>
+__device__ __forceinline__ float ab2_next(const Coefs& C, float wc,
+                                          const float* zm, const float* zp,
+                                          const float* ym, const float* yp,
+                                          const float* xm, const float* xp, float un) {
+  float lap = C.c0 * wc;
+#pragma unroll
+  for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[0][j], zm[j] + zp[j], lap);
+  if (HAS_Y) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[1][j], ym[j] + yp[j], lap);
+  }
+#pragma unroll
+  for (int j = 0; j < R; ++j) lap = __builtin_fmaf(C.w[2][j], xm[j] + xp[j], lap);
+  return un + lap;
+}
+
 // Inside the absorbing layer divide by (1 + st) through the hardware
 // reciprocal; elsewhere (st == 0) the numerator is the result.
 __device__ __forceinline__ float wave_damp(float num, float st) {
@@ -119,8 +145,9 @@ struct SweepAux {
 };
 
 // Kernel modes: the wave sweep forward, forward storing the history, adjoint
-// with imaging; explicit diffusion (one input level, no b, no damping).
-enum : int { MODE_FWD = 0, MODE_HIST = 1, MODE_ADJ = 2, MODE_DIFF = 3 };
+// with imaging; explicit diffusion (one input level, no b, no damping); the
+// two-level Adams-Bashforth diffusion step (single-step kernel only).
+enum : int { MODE_FWD = 0, MODE_HIST = 1, MODE_ADJ = 2, MODE_DIFF = 3, MODE_AB2 = 4 };
 
 // Everything a sweep launch needs (passed by value).
 struct SweepArgs {

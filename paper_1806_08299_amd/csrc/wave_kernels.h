@@ -232,7 +232,8 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
   int blk;
   const SweepArgs& A = shot_args(P, blk);
   constexpr bool HY = (DIM == 3);
-  constexpr bool DF = (MODE == MODE_DIFF);   // diffusion: one input level, no b
+  constexpr bool AB = (MODE == MODE_AB2);    // two-level diffusion: window of w = 3/2 u^n - 1/2 u^{n-1}
+  constexpr bool DF = (MODE == MODE_DIFF) || AB;   // diffusion: no b, no damping, no points
   constexpr int W = 2 * R + 1;
   constexpr bool ROT = W <= kMaxUnrollWUntiled;
   constexpr int TY = HY ? NW * RY : 1;
@@ -315,13 +316,16 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
   // measured equal and keeps one.
   constexpr int NP = (MODE == MODE_FWD) ? 1 : 2;
   static_assert(NP == 1 || !ROT, "a two-plane prefetch needs the shifted window");
-  float pc[NP][RY], pp[NP][RY], pb[NP][RY], ph[NP][HPT];
+  // AB: pc/pb hold u^n/u^{n-1} of the plane entering the window, pp u^n of
+  // the plane being updated, ph/ph2 u^n/u^{n-1} of its halo.
+  float pc[NP][RY], pp[NP][RY], pb[NP][RY], ph[NP][HPT], ph2[AB ? NP : 1][AB ? HPT : 1];
   {
 #pragma unroll
     for (int j = 1; j <= 2 * R; ++j) {   // planes za-R .. za+R-1: logical 0..2R-1 at rotation 1
       const uint32_t so = sg.off(za - R - 1 + j);
 #pragma unroll
-      for (int i = 0; i < RY; ++i) zw[i][j % W] = bload(rc, col[i], so);
+      for (int i = 0; i < RY; ++i)
+        zw[i][j % W] = AB ? ab2_input(bload(rc, col[i], so), bload(rp, col[i], so)) : bload(rc, col[i], so);
     }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
@@ -329,11 +333,14 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
         pc[q][i] = bload(rc, col[i], sc);
-        pp[q][i] = DF ? 0.0f : bload(rp, col[i], s1);
-        pb[q][i] = DF ? 0.0f : bload(rb, col[i], s1);
+        pp[q][i] = AB ? bload(rc, col[i], s1) : (DF ? 0.0f : bload(rp, col[i], s1));
+        pb[q][i] = AB ? bload(rp, col[i], sc) : (DF ? 0.0f : bload(rb, col[i], s1));
       }
 #pragma unroll
-      for (int h = 0; h < HPT; ++h) ph[q][h] = bload(rc, hcol[h], s1);
+      for (int h = 0; h < HPT; ++h) {
+        ph[q][h] = bload(rc, hcol[h], s1);
+        if constexpr (AB) ph2[q][h] = bload(rp, hcol[h], s1);
+      }
     }
 #pragma unroll
     for (int i = 0; i < RY; ++i) zw[i][0] = 0.0f;
@@ -355,24 +362,30 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
     float up[RY], bb[RY], hv[HPT];
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
-      zw[i][(2 * R + rot) % W] = pc[q][i];
+      zw[i][(2 * R + rot) % W] = AB ? ab2_input(pc[q][i], pb[q][i]) : pc[q][i];
       up[i] = pp[q][i];
       bb[i] = pb[q][i];
     }
 #pragma unroll
-    for (int h = 0; h < HPT; ++h) hv[h] = ph[q][h];
+    for (int h = 0; h < HPT; ++h) hv[h] = AB ? ab2_input(ph[q][h], ph2[AB ? q : 0][AB ? h : 0]) : ph[q][h];
     {  // issue the loads of plane z + NP before touching this plane's data
       const uint32_t sc = sg.off(z + NP + R), s1 = sg.off(z + NP);
 #pragma unroll
       for (int i = 0; i < RY; ++i) {
         pc[q][i] = bload(rc, col[i], sc);
-        if constexpr (!DF) {
+        if constexpr (AB) {
+          pp[q][i] = bload(rc, col[i], s1);
+          pb[q][i] = bload(rp, col[i], sc);
+        } else if constexpr (!DF) {
           pp[q][i] = bload(rp, col[i], s1);
           pb[q][i] = bload(rb, col[i], s1);
         }
       }
 #pragma unroll
-      for (int h = 0; h < HPT; ++h) ph[q][h] = bload(rc, hcol[h], s1);
+      for (int h = 0; h < HPT; ++h) {
+        ph[q][h] = bload(rc, hcol[h], s1);
+        if constexpr (AB) ph2[q][h] = bload(rp, hcol[h], s1);
+      }
     }
     float* buf = lds + (z & 1) * PLB;
 #pragma unroll
@@ -426,7 +439,9 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
           const float sty = HY ? damp_term(gy0 + wv * RY + i, A.n1, A.nbl, A.st_coef) : 0.0f;
           st[i] = (stz + sty) + stx[HY ? 0 : i];
         }
-        if constexpr (DF) {
+        if constexpr (AB) {
+          v[i] = ab2_next<R, HY>(A.C, zw[i][(R + rot) % W], zm, zp, ym, yp, xm, xp, up[i]);
+        } else if constexpr (DF) {
           v[i] = diff_next<R, HY>(A.C, zw[i][(R + rot) % W], zm, zp, ym, yp, xm, xp);
         } else {
           v[i] = wave_num<R, HY>(A.C, zw[i][(R + rot) % W], zm, zp, ym, yp, xm, xp, up[i], bb[i], st[i], f, DM,

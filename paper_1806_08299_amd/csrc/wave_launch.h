@@ -47,9 +47,12 @@ hipError_t launch_batch(int R, int kind, int T, int dim, int mode, int shape, co
 WAVE_DECL(1) WAVE_DECL(2) WAVE_DECL(3) WAVE_DECL(4) WAVE_DECL(5) WAVE_DECL(6) WAVE_DECL(7) WAVE_DECL(8)
 #undef WAVE_DECL
 #undef WAVE_DECL1
-// Explicit diffusion (mode 3): single-context sweeps only.
+// Explicit diffusion (mode 3) and the two-level diffusion step (mode 4):
+// single-context sweeps only.
 #define WAVE_DECL(RR)                                                                            \
   hipError_t launch_sweep_r##RR##_m3(int kind, int T, int dim, int shape, const SweepArgs& A, \
+                                     dim3 grid, size_t lds, hipStream_t s);                     \
+  hipError_t launch_sweep_r##RR##_m4(int kind, int T, int dim, int shape, const SweepArgs& A, \
                                      dim3 grid, size_t lds, hipStream_t s);
 WAVE_DECL(1) WAVE_DECL(2) WAVE_DECL(3) WAVE_DECL(4) WAVE_DECL(5) WAVE_DECL(6) WAVE_DECL(7) WAVE_DECL(8)
 #undef WAVE_DECL

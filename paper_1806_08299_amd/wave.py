@@ -112,11 +112,14 @@ class diff_desc(ctypes.Structure):
                 ("shape", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3),
                 ("dt", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("time_tile", ctypes.c_int32), ("skew", ctypes.c_int32),
-                ("tile", ctypes.c_int32 * 2), ("slab", ctypes.c_int32), ("zchunks", ctypes.c_int32)]
+                ("tile", ctypes.c_int32 * 2), ("slab", ctypes.c_int32), ("zchunks", ctypes.c_int32),
+                ("scheme", ctypes.c_int32)]
+
+SCHEMES = {"euler": 0, "ab2": 1}
 
 
 def make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile=-1, skew=0, tile_shape=0,
-                   zchunks=0, tile=None, slab=0) -> diff_desc:
+                   zchunks=0, tile=None, slab=0, scheme="euler") -> diff_desc:
     d = diff_desc()
     shape = tuple(int(s) for s in shape)
     d.ndim = len(shape)
@@ -132,6 +135,7 @@ def make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile=-1, skew=0,
     d.tile[0], d.tile[1] = _tile_of(d.ndim, tile_shape, tile)
     d.slab = int(slab)
     d.zchunks = int(zchunks)
+    d.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
     return d
 
 
@@ -166,7 +170,7 @@ def lib():
             "wave_ai_tight": (dbl, [dbl, i32, i32, P, P, P, dbl]),
             "wave_flops_per_point": (dbl, [i32, i32, i32]),
             "wave_bytes_per_point": (dbl, [i32, i32]),
-            "diff_flops_per_point": (dbl, [i32, i32]),
+            "diff_flops_per_point": (dbl, [i32, i32, i32]),
             "diff_state_bytes": (sz, [P]),
             "diff_init": (i32, [P, P, sz, P, ctypes.POINTER(P)]),
             "diff_forward": (i32, [P, i32, P, P]),
@@ -400,8 +404,8 @@ def wave_destroy(ctx):
         lib().wave_destroy(ctx)
 
 
-def diff_flops_per_point(ndim, space_order) -> float:
-    return float(lib().diff_flops_per_point(ndim, space_order))
+def diff_flops_per_point(ndim, space_order, scheme="euler") -> float:
+    return float(lib().diff_flops_per_point(ndim, space_order, SCHEMES[scheme] if isinstance(scheme, str) else scheme))
 
 
 def diff_state_bytes(desc: diff_desc) -> int:
@@ -543,12 +547,13 @@ class WaveFn(torch.autograd.Function):
 
 class DiffOp:
     """Explicit diffusion u <- u + dt a (L u) (the Laplace-operator workload)
-    on the sweep engine: a diffusion context plus its two-level state."""
+    on the sweep engine, or with scheme="ab2" its two-level Adams-Bashforth
+    form: a diffusion context plus its state."""
 
     def __init__(self, shape, spacing, dt, alpha, space_order, time_tile=-1, skew=0, tile_shape=0, zchunks=0,
-                 device="cuda", tile=None, slab=0):
+                 device="cuda", tile=None, slab=0, scheme="euler"):
         self.desc = make_diff_desc(shape, spacing, dt, alpha, space_order, time_tile, skew, tile_shape, zchunks,
-                                   tile=tile, slab=slab)
+                                   tile=tile, slab=slab, scheme=scheme)
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
         self.device = torch.device(device)

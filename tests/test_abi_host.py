@@ -73,11 +73,20 @@ def test_flop_and_byte_counts(W):
     assert W.diff_flops_per_point(3, 8) == 2 + 3 * 3 * 4
     assert W.wave_bytes_per_point(-1, 3) == 8.0
     assert W.wave_bytes_per_point(4, 3) == 2.0
+    # the two-level step: also 3/2 u^n - 1/2 u^{n-1}; reads two levels, writes one
+    # (two per time tile)
+    assert W.diff_flops_per_point(3, 8, "ab2") == 5 + 3 * 3 * 4
+    assert W.wave_bytes_per_point(-1, 4) == 12.0
+    assert W.wave_bytes_per_point(8, 4) == 2.0
 
 
 def test_diff_state_bytes_and_validation(W):
     d = W.make_diff_desc((48, 40, 72), 0.1, 1e-4, 0.5, 8)
     assert W.diff_state_bytes(d) >= 2 * 4 * 48 * 40 * 72
+    d2 = W.make_diff_desc((48, 40, 72), 0.1, 1e-4, 0.5, 8, scheme="ab2")
+    assert W.diff_state_bytes(d2) >= 3 * 4 * 48 * 40 * 72 > W.diff_state_bytes(d)
+    d2.scheme = 2
+    assert W.diff_state_bytes(d2) == 0
     for bad in (dict(space_order=7), dict(ndim=1), dict(dt=-1.0)):
         dd = W.make_diff_desc((48, 40, 72), 0.1, 1e-4, 0.5, 8)
         for k, v in bad.items():

@@ -1,0 +1,118 @@
+"""GPU parity of the two-level (delta_t = 2) Laplace-operator stencil: the
+two-step Adams-Bashforth rule u^{n+1} = u^n + dt a (3/2 L u^n - 1/2 L u^{n-1}),
+u^{-1} = u^0 (evaluation chapter, "Time-tiling with larger time
+dependences"), through the C ABI (diff_init with scheme 1, diff_forward).
+
+* FP32 GPU vs the FP64 oracle (oracle.diffuse_ab2): relative L2 <= 1e-5 and a
+  per-element bound, at orders 2..16 in 3D and 2D on ragged grids;
+* the skewed schedule (any depth, slabs thinner than skew + radius, slabs
+  that do not divide the grid) bitwise equal to the untiled sweep;
+* the first step is bitwise the one-level (forward-Euler) step;
+* the default schedule, register tiles refused, the halved stability limit,
+  nt = 0, the autotuner.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import waveinputs as wi
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a).astype(np.float64) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def _work(shape, so, nt, seed):
+    """The Laplace-operator inputs with dt at 0.9 of the two-level limit."""
+    w = wi.laplace(shape=shape, so=so, nt=nt, seed=seed)
+    return w, w.dt / 2.0
+
+
+def _op(w, dt, **kw):
+    from paper_1806_08299_amd import DiffOp
+    return DiffOp(w.shape, w.spacing, dt, w.alpha, w.so, scheme="ab2", **kw)
+
+
+def _ref(w, dt):
+    g = oracle.Grid(w.shape, w.spacing, dt, w.so)
+    return oracle.diffuse_ab2(g, w.alpha, w.nt, w.u0.astype(np.float64))
+
+
+def _check(got, ref):
+    assert rel(got, ref) <= TOL
+    # per element: no point off by more than 1e-5 of the field's scale
+    assert np.abs(got.astype(np.float64) - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("so", [2, 4, 6, 8, 12, 16])
+def test_ab2_against_oracle_3d(so):
+    w, dt = _work((37, 41, 70), so, 13, seed=40 + so)
+    op = _op(w, dt, time_tile=-1)
+    got = op.forward(w.nt, torch.from_numpy(w.u0).cuda()).cpu().numpy()
+    _check(got, _ref(w, dt))
+
+
+@pytest.mark.parametrize("so", [4, 16])
+def test_ab2_against_oracle_2d(so):
+    w, dt = _work((61, 1100), so, 17, seed=60 + so)
+    op = _op(w, dt, time_tile=-1)
+    got = op.forward(w.nt, torch.from_numpy(w.u0).cuda()).cpu().numpy()
+    _check(got, _ref(w, dt))
+
+
+@pytest.mark.parametrize("so", [2, 8, 16])
+def test_ab2_skewed_bitwise(so):
+    R = so // 2
+    w, dt = _work((53, 30, 75), so, 13, seed=70 + so)
+    u0 = torch.from_numpy(w.u0).cuda()
+    op = _op(w, dt, time_tile=-1)
+    ref = op.forward(w.nt, u0).cpu().numpy()
+    _check(ref, _ref(w, dt))
+    for T, Z, skew, zc in [(2, 8, 0, 0), (5, max(1, R), 0, 0), (13, 30, R + 2, 2), (4, 100, 0, 1)]:
+        print("ab2 so %d skewed T=%d slab=%d skew=%d zchunks=%d" % (so, T, Z, skew, zc), flush=True)
+        op.set_schedule(T, skew, 0, zc, slab=Z)
+        got = op.forward(w.nt, u0).cpu().numpy()
+        assert np.array_equal(got, ref), (so, T, Z, skew, zc)
+
+
+def test_ab2_first_step_is_the_euler_step():
+    from paper_1806_08299_amd import DiffOp
+    w, dt = _work((20, 33, 70), 8, 1, seed=80)
+    u0 = torch.from_numpy(w.u0).cuda()
+    a = _op(w, dt, time_tile=-1).forward(1, u0).cpu().numpy()
+    e = DiffOp(w.shape, w.spacing, dt, w.alpha, w.so, time_tile=-1).forward(1, u0).cpu().numpy()
+    assert np.array_equal(a, e)
+    z = _op(w, dt, time_tile=-1).forward(0, u0).cpu().numpy()
+    assert np.array_equal(z, w.u0)
+
+
+def test_ab2_schedules_and_limits():
+    from paper_1806_08299_amd import DiffOp, WaveError
+    w, dt = _work((60, 40, 70), 4, 9, seed=81)
+    op = _op(w, dt, time_tile=0)
+    assert op.schedule().T == 8 and op.schedule().slab == 48       # default at radius 2 in 3D
+    op8 = _op(wi.laplace(shape=(30, 30, 70), so=8, nt=3, seed=2), dt / 10.0, time_tile=0)
+    assert op8.schedule().T == -1                                  # untiled beyond radius 2
+    with pytest.raises(WaveError) as e:
+        op.set_schedule(2, 0, 2, 0)                                # register tiles: not for two levels
+    assert e.value.status == -7
+    # between the two-level limit and the one-level limit: only scheme 0 accepts
+    # it (order 4: rho = 16/3, so dt a 3 rho / h^2 = 1.5 at dt = 1.5 / 16)
+    dt_mid = 1.5 / (w.alpha * 3 * 16.0 / 3.0)
+    DiffOp(w.shape, w.spacing, dt_mid, w.alpha, w.so)
+    with pytest.raises(WaveError) as e:
+        _op(w, dt_mid)
+    assert e.value.status == -3
+    # the autotuner keeps an available schedule, and the result stays bitwise
+    u0 = torch.from_numpy(w.u0).cuda()
+    op.set_schedule(-1)
+    ref = op.forward(w.nt, u0).cpu().numpy()
+    op.autotune(trial_steps=8, repeats=1)
+    sch = op.schedule()
+    assert sch.T == -1 or sch.slab > 0
+    assert np.array_equal(op.forward(w.nt, u0).cpu().numpy(), ref)
