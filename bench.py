@@ -141,6 +141,33 @@ def autotune(op, trial_steps=40):
     return wave_autotune(op.ctx, trial_steps, 2, 8, sc)
 
 
+def guided_vs_exhaustive(op, w, wav, stream, trial_steps=40, keep=10):
+    """The estimator-guided autotuner against the exhaustive one on the same
+    context: candidates timed, tuning wall time, and the rate of each kept
+    schedule over the full run."""
+    import torch
+    from paper_1806_08299_amd.wave import wave_autotune, wave_autotune_guided, wave_scratch_bytes
+    out = {}
+    sc = op.scratch(wave_scratch_bytes(op.ctx, trial_steps, 0, 0, 0, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wave_autotune(op.ctx, trial_steps, 2, 8, sc)
+    t_ex = time.perf_counter() - t0
+    ex = op.schedule()
+    out["exhaustive"] = {"schedule": sched_dict(ex), "tuning_s": round(t_ex, 2),
+                         "value": round(_rate(op, w.nt, w, wav, stream, 1), 1)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, n = wave_autotune_guided(op.ctx, trial_steps, 2, 8, keep, sc)
+    t_gd = time.perf_counter() - t0
+    gd = op.schedule()
+    out["guided"] = {"schedule": sched_dict(gd), "tuning_s": round(t_gd, 2), "timed_candidates": n, "keep": keep,
+                     "value": round(_rate(op, w.nt, w, wav, stream, 1), 1)}
+    out["guided_over_exhaustive"] = round(out["guided"]["value"] / out["exhaustive"]["value"], 3)
+    op._scratch = None
+    return out
+
+
 def kernel_name(sched, so) -> str:
     T, slab, tile = sched[0], sched[5], sched[4]
     if T < 0:
@@ -653,11 +680,12 @@ def tiling_factor(so, dev, stream, nt=100, n=512):
              for T in range(1, wave_tiled_max_depth(so, 3, tile=t) + 1) for zc in (0, 16, 32)]
     cands += [Schedule(T, 0, 0, 2, (0, 0), Z) for T in (4, 8) for Z in (48, 64)]
     tiled = max((_rate(op, nt, w, wav, stream, 2, c), c) for c in cands)
+    guided = guided_vs_exhaustive(op, w, wav, stream, trial_steps=20)
     del op
     torch.cuda.empty_cache()
     return {"space_order": so, "untiled": round(untiled[0], 1), "untiled_zchunks": untiled[1],
             "tiled": round(tiled[0], 1), "tiled_schedule": sched_dict(tiled[1]),
-            "factor": round(tiled[0] / untiled[0], 3)}
+            "factor": round(tiled[0] / untiled[0], 3), "autotuners": guided}
 
 
 def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16)):

@@ -100,10 +100,17 @@ typedef struct wave_desc {
 
 typedef struct wave_ctx wave_ctx;
 
-/* Bytes of the persistent device state for `d` (0 if d is invalid). */
+/* Bytes of the persistent device state for `d` (0 if d is invalid): four
+ * time levels (two ping-pong pairs of the leapfrog scheme's two levels; the
+ * paper's time buffer of the Devito chapter, "Time-buffering", holds the
+ * dependence depth plus the time tile) and b = dt^2/m.  Host-only. */
 size_t wave_state_bytes(const wave_desc* d);
 
-/* Validate `d`, build the schedule and the per-axis damping tables, and derive
+/* Set up the operator of the paper's problem statement (Devito chapter: grid,
+ * spacing, time step, space order, then the schedule parameters of
+ * "Parameterisation"; the acoustic-wave operator of the evaluation chapter,
+ * "Performance of the acoustic wave equation operator").
+ * Validate `d`, build the schedule and the per-axis damping tables, and derive
  * b = dt^2/m from the model m_dev [N] (s^2/m^2, device, must stay > 0).  The
  * CFL check uses max velocity 1/sqrt(min m): this call synchronises the
  * stream once.  time_tile == 0 picks the default schedule (see wave_desc);
@@ -112,7 +119,9 @@ size_t wave_state_bytes(const wave_desc* d);
 wave_status wave_init(const wave_desc* d, const float* m_dev, void* state_dev, size_t state_bytes,
                       void* hip_stream, wave_ctx** out);
 
-/* Replace the model (same shape); re-checks the CFL limit (synchronises).
+/* Replace the model m (the wave operator's coefficient field; evaluation
+ * chapter, acoustic wave equation operator) of the same shape; re-checks the
+ * CFL limit (synchronises).
  * Every entry must be a positive finite number (WAVE_EINVAL otherwise,
  * NaN included). */
 wave_status wave_set_model(wave_ctx* ctx, const float* m_dev);
@@ -132,7 +141,10 @@ wave_status wave_set_schedule(wave_ctx* ctx, int32_t time_tile, int32_t skew, co
 wave_status wave_get_schedule(const wave_ctx* ctx, int32_t* time_tile, int32_t* skew, int32_t* tile,
                               int32_t* slab, int32_t* zchunks);
 
-/* Scratch bytes needed by wave_forward (adjoint = 0), by wave_forward with
+/* Memory plan of a call (the library allocates nothing; the caller's buffer
+ * holds what the paper's generated code keeps in its time buffer and point
+ * tables).  Host-only.
+ * Scratch bytes needed by wave_forward (adjoint = 0), by wave_forward with
  * checkpoints followed by wave_adjoint_grad (adjoint = 1), or by one shot of
  * wave_batch with a gradient (adjoint = 2: also the residual traces) for nt
  * steps with nsrc sources and nrec receivers; ckpt_every = K > 0 keeps a
@@ -142,7 +154,11 @@ wave_status wave_get_schedule(const wave_ctx* ctx, int32_t* time_tile, int32_t* 
 size_t wave_scratch_bytes(const wave_ctx* ctx, int32_t nt, int32_t nsrc, int32_t nrec, int32_t ckpt_every,
                           int32_t adjoint);
 
-/* Forward modelling, nt steps.
+/* Forward modelling, nt steps: the time loop of the paper's operator under
+ * the context's schedule (implementation chapter, "Time-tiling"; untiled,
+ * register-tiled or skewed), with source injection and receiver sampling
+ * inside the tiles (left to future work in the paper: implementation
+ * chapter, the source and receiver loops; conclusion, future work).
  *   src_xyz  host [nsrc][ndim];  wavelet_dev device [nt][nsrc]  (q_s^n drives u^{n+1})
  *   rec_xyz  host [nrec][ndim];  rec_dev device [nt][nrec] out (d^n samples u^{n+1}) or NULL
  *   u_init_dev  device [2][N] = (u^0, u^{-1}) or NULL for zeros
@@ -157,7 +173,10 @@ wave_status wave_forward(wave_ctx* ctx, int32_t nt,
                          const float* u_init_dev, float* u_final_dev,
                          int32_t ckpt_every, void* scratch_dev, size_t scratch_bytes);
 
-/* Adjoint sweep and gradient, zero initial state.
+/* Adjoint sweep and gradient, zero initial state (not in the paper: the
+ * discrete adjoint of the same leapfrog operator, run backwards in time under
+ * the same schedules, with the imaging condition fused; every recomputed
+ * forward segment and every adjoint step use the schedule of the context).
  *   resid_dev       device [nt][nrec]: dJ/dd (e.g. d - d_obs)
  *   grad_m_dev      device [N] out: dJ/dm
  *   grad_wavelet_dev device [nt][nsrc] out: dJ/dq, or NULL
@@ -213,17 +232,42 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
                        const float* const* dobs_dev, float* const* grad_m_dev,
                        int32_t ckpt_every, void* const* scratch_dev, const size_t* scratch_bytes);
 
-/* Autotune the schedule (T, skew, tile shape, zchunks) on this context's
- * model by timing short trial sweeps (minimum of `repeats` trials per
- * candidate): first every depth T <= max_T and tile shape at the default
- * number of axis-0 segments, then 1..32 axis-0 segments for the five fastest.
- * Keeps the fastest.  Synchronises; needs scratch for `trial_steps` forward
- * steps without sources (wave_scratch_bytes(ctx, trial_steps, 0, 0, 0, 0)).
- * On a diffusion context (diff_init) the trials are diff_forward calls from
- * a zero field between two levels in the scratch (2 N floats, also what
+/* Autotune the schedule on this context's model by timing short trial
+ * sweeps, as the paper's auto-tuner times candidate tile sizes
+ * (implementation chapter, "Auto-tuning"; evaluation chapter, "Auto-tuner
+ * iterations" and "Time-tiling parameters").  Minimum of `repeats` trials per
+ * candidate.  Phase 1: the untiled sweep, every register tile of the table at
+ * every built depth T <= max_T, and the skewed schedule at T = 2, 4, ... <=
+ * max_T (16 if max_T = 0) on slabs of 32 and 64 planes, all at the default
+ * number of axis-0 segments.  Phase 2: 1..32 axis-0 segments for the five
+ * fastest.  Phase 3: the skewing factor (r, a multiple of 4, 2r) of the best
+ * register-tiled schedule, or the slab thickness and depth of the best skewed
+ * one (the paper's skew experiment, "Effect of the skewing factor").  Keeps
+ * the fastest.  Synchronises; needs scratch for `trial_steps` forward steps
+ * without sources (wave_scratch_bytes(ctx, trial_steps, 0, 0, 0, 0)).  On a
+ * diffusion context (diff_init) the trials are diff_forward calls from a zero
+ * field between two levels in the scratch (2 N floats, also what
  * wave_scratch_bytes returns for such a context). */
 wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
                           void* scratch_dev, size_t scratch_bytes, double* best_seconds_per_step);
+
+/* The estimator-guided autotuner the paper proposes (evaluation chapter,
+ * "Minimising runtime based on tile size choices" and "Further uses for an
+ * arithmetic intensity estimator"; conclusion, future work): instead of
+ * timing every candidate of phase 1, it times four anchors (the untiled
+ * sweep, the shallowest and the deepest register tile of 32 x 64, one skewed
+ * schedule), calibrates on them a model of every candidate's time -- the
+ * larger of its memory side (compulsory bytes per point-update x the
+ * workgroup's halo re-load factor x the ratio of the naive to the tight
+ * intensity bound, over the bandwidth the untiled anchor achieved) and its
+ * compute side (the redundant work of a register tile x the register
+ * anchors' cost interpolated in T, or the single-step kernel's) -- and times only the
+ * `keep` >= 1 candidates the model ranks fastest; phase 2 then covers the two
+ * fastest, phase 3 as in wave_autotune.  *timed_trials (may be NULL) receives
+ * the number of candidates timed.  Arguments and errors as wave_autotune. */
+wave_status wave_autotune_guided(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
+                                 int32_t keep, void* scratch_dev, size_t scratch_bytes,
+                                 double* best_seconds_per_step, int32_t* timed_trials);
 
 /* Arithmetic-intensity estimators of the evaluation chapter ("Arithmetic
  * intensity under time-tiling").  Host-only, no device access.
@@ -254,12 +298,17 @@ int32_t wave_tiled_max_depth(int32_t space_order, int32_t ndim, int32_t ey, int3
  * Returns WAVE_EINVAL past the end of the table or for a bad ndim. */
 wave_status wave_tile_extent(int32_t ndim, int32_t index, int32_t* ey, int32_t* ex);
 
-/* Flops per point-update of the sweep (adds + multiplies, FMA = 2) for order
- * so in ndim dimensions, and compulsory HBM bytes per point-update of the
- * schedule (T = -1 untiled; damping computed from indices) for mode 0
- * (forward), 1 (forward storing the history, +4 B), 2 (adjoint reading the
- * history and updating the gradient at every stage, +12 B) or 3 (explicit
- * diffusion: read one level, write one level per launch, 8/T B). Host-only. */
+/* The counts behind the roofline analysis of the evaluation chapter
+ * ("Arithmetic intensity under time-tiling", compulsory memory traffic):
+ * flops per point-update of the sweep (adds + multiplies, FMA = 2) for order
+ * so in ndim dimensions, and compulsory HBM bytes per point-update of a
+ * schedule of depth time_tile (T = -1 untiled; damping computed from
+ * indices; the register-tiled and the skewed schedules move the same
+ * compulsory bytes) for mode 0 (forward), 1 (forward storing the history,
+ * +4 B), 2 (adjoint reading the history and updating the gradient at every
+ * stage, +12 B), 3 (explicit diffusion: read one level, write one level per
+ * launch, 8/T B) or 4 (the two-level diffusion step: 12 B untiled, 16/T B
+ * per time tile).  Host-only. */
 double wave_flops_per_point(int32_t ndim, int32_t space_order, int32_t damped);
 double wave_bytes_per_point(int32_t time_tile, int32_t mode);
 
@@ -298,8 +347,8 @@ typedef struct diff_desc {
                             rule u^{n+1} = u^n + dt a (3/2 L u^n - 1/2 L u^{n-1}) with
                             u^{-1} = u^0.  Scheme 1 runs the untiled sweep or the skewed
                             schedule (slab > 0; WAVE_EUNSUPPORTED for register tiles); its
-                            default (time_tile = 0) is skewed, T = 8 on slabs of 48 planes,
-                            up to radius 2 in 3D, untiled otherwise; its stability limit
+                            default (time_tile = 0) is skewed, T = 16 on slabs of 64 planes,
+                            up to radius 2 in 3D, untiled otherwise (measured); its stability limit
                             is half that of scheme 0 */
 } diff_desc;
 
@@ -346,6 +395,9 @@ wave_status wave_forward_static(wave_ctx* ctx, int32_t nt,
                                 int32_t nrec, const double* rec_xyz, float* rec_dev,
                                 const float* u_init_dev, float* u_final_dev);
 
+/* Library housekeeping (no passage of the paper): the text of a status, the
+ * message of the last failed call on a context, and the release of a
+ * context's host resources (the caller frees its device buffers after). */
 const char* wave_strerror(wave_status s);
 const char* wave_last_error(const wave_ctx* ctx);
 void wave_destroy(wave_ctx* ctx);

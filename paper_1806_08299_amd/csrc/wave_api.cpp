@@ -1442,9 +1442,88 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const 
   return WAVE_OK;
 }
 
-wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, void* scratch,
-                          size_t scratch_bytes, double* best) {
-  if (!c || trial_steps < 1 || repeats < 1) return WAVE_EINVAL;
+}  // extern "C"
+
+namespace {
+
+struct Cand { int T, skew, shape, slab, zc; };
+
+// Model of one candidate's cost per point-update, from the schedule's
+// geometry alone: compulsory bytes x the workgroup's halo re-load x the
+// tight bound's correction (memory side), and the redundant work of a
+// register tile (compute side).  The guided autotuner calibrates the two
+// sides' rates on the GPU from three timed anchors.
+struct CandModel {
+  double mem;     // bytes per point-update the schedule is expected to move
+  double work;    // computed points per useful point-update
+  int kind;       // 0: single-step kernel over the whole grid, 1: register-tiled, 2: skewed
+};
+
+CandModel cand_model(wave_ctx* c, const Cand& k) {
+  CandModel M{};
+  const int R = c->R;
+  const int mode = c->eq == 0 ? 0 : (c->eq == 1 ? 3 : 4);
+  const double bc = wave_bytes_per_point(k.T, mode);
+  const int shape = (c->dim == 3) ? k.shape : 0;
+  double h = 1.0, rho = 1.0, t0 = (double)c->n0;
+  int ey = 1, ex = 1;
+  if (k.T >= 1 && k.slab == 0) {
+    M.kind = 1;
+    const BlockShape bs = block_shape(KIND_TILED, c->dim, shape);
+    ey = bs.ey;
+    ex = bs.ex;
+    const int H = k.skew * k.T;
+    const double cy = c->dim == 3 ? (double)(bs.ey - 2 * H) : 1.0, cx = (double)(bs.ex - 2 * H);
+    rho = (c->dim == 3 ? (double)bs.ey : 1.0) * (double)bs.ex / std::max(1.0, cy * cx);
+    h = rho;   // every level the tile loads is loaded over the extended tile
+    Plan p;
+    const int ok = c->shape, oT = c->T, os = c->skew, osl = c->slab, oz = c->zchunks;
+    c->shape = shape ? shape : 1;
+    c->T = k.T;
+    c->skew = k.skew;
+    c->slab = 0;
+    c->zchunks = k.zc;
+    if (make_plan(c, KIND_TILED, k.T, p) == WAVE_OK) {
+      t0 = p.zchunk;
+      h *= (p.zchunk + 2.0 * (k.T + 1) * R) / p.zchunk;   // pipeline fill of each segment
+    }
+    c->shape = ok; c->T = oT; c->skew = os; c->slab = osl; c->zchunks = oz;
+  } else {
+    M.kind = k.slab > 0 ? 2 : 0;
+    const BlockShape bs = block_shape(KIND_UNTILED, c->dim, 0);
+    ey = bs.ey;
+    ex = bs.ex;
+    // one of the streams (the input level) is read with its halo
+    const double ext = (c->dim == 3 ? (bs.ey + 2.0 * R) / bs.ey : 1.0) * (bs.ex + 2.0 * R) / bs.ex;
+    h = 1.0 + (ext - 1.0) / (mode == 0 ? 4.0 : 2.0);
+    const int64_t len = k.slab > 0 ? std::min<int64_t>(k.slab, c->n0) : c->n0;
+    const int64_t base = (int64_t)((c->n2 + bs.ex - 1) / bs.ex) * ((c->n1 + bs.ey - 1) / bs.ey);
+    int zc = k.zc > 0 ? k.zc : auto_zchunks(c, base, KIND_UNTILED, 1, len);
+    zc = (int)std::max<int64_t>(1, std::min<int64_t>(zc, len));
+    const double seg = (double)((len + zc - 1) / zc);
+    t0 = k.slab > 0 ? (double)k.slab : seg;
+    h *= 1.0 + (2.0 * R / seg) / (mode == 0 ? 4.0 : 2.0);   // window fill of each segment
+  }
+  // the paper's tight bound: faces of the tiles that do not fit one L2 are
+  // re-loaded; its ratio to the naive bound scales the compulsory bytes
+  const double D[3] = {(double)c->n0, (double)c->n1, (double)c->n2};
+  const double del[3] = {(double)R, (double)R, (double)R};
+  const double tl[3] = {t0, (double)ey, (double)ex};
+  const int nd = c->dim;
+  const double Dn[3] = {D[0], nd == 3 ? D[1] : D[2], D[2]};
+  const double tn[3] = {tl[0], nd == 3 ? tl[1] : tl[2], tl[2]};
+  const int Tt = std::max(1, k.T);
+  const double naive = wave_ai_naive(1.0, Tt);
+  const double tight = wave_ai_tight(1.0, Tt, nd, Dn, del, tn, 4.0 * 1024 * 1024 / 4.0);
+  const double corr = (std::isfinite(tight) && tight > 0.0) ? naive / tight : 1.0;
+  M.mem = bc * h * corr;
+  M.work = rho;
+  return M;
+}
+
+wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, int keep, void* scratch,
+                          size_t scratch_bytes, double* best, int* timed_count) {
+  if (!c || trial_steps < 1 || repeats < 1 || keep < 0) return WAVE_EINVAL;
   // Wave equation: trial forwards with the scratch layout of wave_forward.
   // Diffusion: trial diff_forward calls from a zero field in the first half
   // of the scratch into its second half.
@@ -1458,15 +1537,16 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
     wave_status fs = fill(c, (float*)scratch, c->N, 0.0f);
     if (fs != WAVE_OK) return fs;
   }
-  struct Cand { int T, skew, shape, slab, zc; };
   std::vector<Cand> cands;
   cands.push_back({-1, c->R, c->shape ? c->shape : 1, 0, 0});
   // register-tiled: every built tile and depth at the minimum skew
   const int nshapes = c->dim == 3 ? kNumShapes3D : 1;
-  for (int si = 1; si <= nshapes; ++si) {
-    const int sh = c->dim == 3 ? si : 0;
-    const int tm = std::min<int>(max_T > 0 ? max_T : 8, tiled_tmax(c->R, c->dim, sh));
-    for (int T = 1; T <= tm; ++T) cands.push_back({T, c->R, sh, 0, 0});
+  if (c->eq != 2) {
+    for (int si = 1; si <= nshapes; ++si) {
+      const int sh = c->dim == 3 ? si : 0;
+      const int tm = std::min<int>(max_T > 0 ? max_T : 8, tiled_tmax(c->R, c->dim, sh));
+      for (int T = 1; T <= tm; ++T) cands.push_back({T, c->R, sh, 0, 0});
+    }
   }
   // skewed: depths 2..16 (up to max_T) on slabs of 32 and 64 planes
   const int tskew = max_T > 0 ? max_T : 16;
@@ -1496,14 +1576,72 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
     return tmin;
   };
   auto better = [](const std::pair<double, Cand>& x, const std::pair<double, Cand>& y) { return x.first < y.first; };
-  // Phase 1: kind, depth and tile at the default number of axis-0 segments.
+  int ntimed = 0;
+  auto timed_one = [&](const Cand& k) {
+    ++ntimed;
+    return time_one(k);
+  };
+  // Phase 1: kind, depth and tile at the default number of axis-0 segments:
+  // every candidate, or (keep > 0) the ones an intensity model calibrated on
+  // three timed anchors ranks fastest.
   std::vector<std::pair<double, Cand>> timed;
-  for (const Cand& k : cands) timed.push_back({time_one(k), k});
+  if (keep == 0) {
+    for (const Cand& k : cands) timed.push_back({timed_one(k), k});
+  } else {
+    // anchors: the untiled sweep (memory-bound on MI355X at every order:
+    // gives the rate of the memory side), the shallowest register tile
+    // (compute-bound: the register kernels' cost per computed point) and a
+    // skewed schedule (the single-step kernel's cost when its data is cached)
+    // (the register kernels' cost per computed point changes with the depth:
+    // two register anchors on the 32 x 64 tile, T = 1 and the deepest built,
+    // and a linear interpolation in T between them)
+    std::vector<Cand> anchors = {cands[0]};
+    int r_lo = -1, r_hi = -1, r_sk = -1;
+    for (const Cand& k : cands)
+      if (k.slab == 0 && k.T >= 1 && (c->dim == 2 || k.shape == 2)) {
+        if (r_lo < 0) { r_lo = (int)anchors.size(); anchors.push_back(k); }
+        else if (k.T > anchors[r_lo].T) { if (r_hi < 0) { r_hi = (int)anchors.size(); anchors.push_back(k); } else anchors[r_hi] = k; }
+      }
+    for (const Cand& k : cands)
+      if (k.slab > 0) { r_sk = (int)anchors.size(); anchors.push_back(k); break; }
+    std::vector<double> t_a(anchors.size());
+    std::vector<CandModel> m_a(anchors.size());
+    for (size_t i = 0; i < anchors.size(); ++i) {
+      t_a[i] = timed_one(anchors[i]);
+      m_a[i] = cand_model(c, anchors[i]);
+      timed.push_back({t_a[i], anchors[i]});
+    }
+    const double bw = m_a[0].mem / t_a[0];                  // the untiled sweep: memory-bound
+    // compute time per unit of work: the single-step kernel (the faster of
+    // the untiled and skewed anchors bounds it), the register kernels by depth
+    double phi_single = t_a[0];
+    if (r_sk >= 0 && t_a[r_sk] < 1e300) phi_single = std::min(phi_single, t_a[r_sk]);
+    auto phi_reg = [&](int T) {
+      if (r_lo < 0) return 1e300;
+      const double lo = t_a[r_lo] / m_a[r_lo].work;
+      if (r_hi < 0 || t_a[r_hi] >= 1e300) return lo;
+      const double hi = t_a[r_hi] / m_a[r_hi].work;
+      const double f = (double)(T - anchors[r_lo].T) / (double)(anchors[r_hi].T - anchors[r_lo].T);
+      return lo + std::min(1.0, std::max(0.0, f)) * (hi - lo);
+    };
+    std::vector<std::pair<double, Cand>> pred;
+    for (const Cand& k : cands) {
+      bool is_anchor = false;
+      for (const Cand& a : anchors)
+        is_anchor |= (a.T == k.T && a.shape == k.shape && a.slab == k.slab && a.skew == k.skew);
+      if (is_anchor) continue;
+      const CandModel m = cand_model(c, k);
+      const double cmp = m.kind == 1 ? m.work * phi_reg(k.T) : phi_single;
+      pred.push_back({std::max(m.mem / bw, cmp), k});
+    }
+    std::stable_sort(pred.begin(), pred.end(), better);
+    for (size_t i = 0; i < pred.size() && (int)i < keep; ++i) timed.push_back({timed_one(pred[i].second), pred[i].second});
+  }
   std::stable_sort(timed.begin(), timed.end(), better);
   double best_t = timed.empty() ? 1e300 : timed[0].first;
   Cand bc = timed.empty() ? Cand{oT, os, osh, osl, oz} : timed[0].second;
   auto consider = [&](const Cand& k) {
-    const double t = time_one(k);
+    const double t = timed_one(k);
     if (t < best_t) {
       best_t = t;
       bc = k;
@@ -1514,7 +1652,7 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
   // schedule that phase 1 ranks behind the untiled sweep can overtake it
   // with more segments.
   const int zcs[8] = {1, 2, 4, 8, 12, 16, 24, 32};
-  for (size_t t = 0; t < std::min<size_t>(5, timed.size()); ++t) {
+  for (size_t t = 0; t < std::min<size_t>(keep == 0 ? 5 : 2, timed.size()); ++t) {
     if (timed[t].first >= 1e300) break;
     for (int z : zcs) {
       if (z > c->n0) break;
@@ -1559,8 +1697,29 @@ wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int
     return s;
   }
   if (best) *best = best_t / trial_steps;
+  if (timed_count) *timed_count = ntimed;
   return WAVE_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, void* scratch,
+                          size_t scratch_bytes, double* best) {
+  return autotune_impl(c, trial_steps, repeats, max_T, 0, scratch, scratch_bytes, best, nullptr);
+}
+
+wave_status wave_autotune_guided(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, int32_t keep,
+                                 void* scratch, size_t scratch_bytes, double* best, int32_t* timed) {
+  if (keep < 1) return c ? fail(c, WAVE_EINVAL, "keep must be >= 1") : WAVE_EINVAL;
+  int n = 0;
+  const wave_status s = autotune_impl(c, trial_steps, repeats, max_T, keep, scratch, scratch_bytes, best, &n);
+  if (timed) *timed = n;
+  return s;
+}
+
+
 
 // ----------------------------------------------------------- estimators
 
@@ -1681,9 +1840,10 @@ static double diff_stability(const diff_desc* d) {
 static int diff_levels(const diff_desc* d) { return d->scheme == 1 ? 3 : 2; }
 
 // Default skewed schedule of the two-level step (0: untiled), from
-// measurements on MI355X.
-static int ab2_default_depth(const wave_ctx* c) { return (c->dim == 3 && c->R <= 2) ? 8 : 0; }
-static int ab2_default_slab(const wave_ctx* c) { (void)c; return 48; }
+// measurements on MI355X (500^3, 32 steps: T = 16 on 64-plane slabs 1.32x
+// the untiled sweep at order 2, 1.24x at order 4; 0.95x at order 8).
+static int ab2_default_depth(const wave_ctx* c) { return (c->dim == 3 && c->R <= 2) ? 16 : 0; }
+static int ab2_default_slab(const wave_ctx* c) { (void)c; return 64; }
 
 
 size_t diff_state_bytes(const diff_desc* d) {

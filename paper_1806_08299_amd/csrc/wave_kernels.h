@@ -71,6 +71,9 @@ constexpr uint32_t kOOB = 0x80000000u;      // column offset of an out-of-grid l
 #ifndef WAVE_MAX_UNROLL_W_UNTILED
 #define WAVE_MAX_UNROLL_W_UNTILED 0
 #endif
+#ifndef WAVE_FWD_PREFETCH
+#define WAVE_FWD_PREFETCH 1   // planes of loads in flight in the plain forward single-step sweep
+#endif
 constexpr int kMaxUnrollW = WAVE_MAX_UNROLL_W;   // tiled: unroll the z loop by the window for 2R+1 <= this
 constexpr int kMaxUnrollWUntiled = WAVE_MAX_UNROLL_W_UNTILED;   // untiled: likewise (0: always shift)
 
@@ -314,7 +317,7 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
   // registers or many streams: diffusion +3-4 %, the recompute storing the
   // history and the adjoint with imaging -5 % time; the plain wave forward
   // measured equal and keeps one.
-  constexpr int NP = (MODE == MODE_FWD) ? 1 : 2;
+  constexpr int NP = (MODE == MODE_FWD) ? WAVE_FWD_PREFETCH : 2;
   static_assert(NP == 1 || !ROT, "a two-plane prefetch needs the shifted window");
   // AB: pc/pb hold u^n/u^{n-1} of the plane entering the window, pp u^n of
   // the plane being updated, ph/ph2 u^n/u^{n-1} of its halo.

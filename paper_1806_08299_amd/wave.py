@@ -164,6 +164,7 @@ def lib():
             "wave_adjoint_grad": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, i32, P, sz]),
             "wave_batch": (i32, [P, i32, i32, P, P, P, P, P, P, P, P, i32, P, P]),
             "wave_autotune": (i32, [P, i32, i32, i32, P, sz, P]),
+            "wave_autotune_guided": (i32, [P, i32, i32, i32, i32, P, sz, P, P]),
             "wave_tiled_max_depth": (i32, [i32, i32, i32, i32]),
             "wave_tile_extent": (i32, [i32, i32, P, P]),
             "wave_ai_naive": (dbl, [dbl, i32]),
@@ -304,6 +305,17 @@ def wave_autotune(ctx, trial_steps, repeats, max_T, scratch):
                              scratch.numel() * scratch.element_size(), ctypes.byref(best))
     _check(st, ctx)
     return best.value
+
+
+def wave_autotune_guided(ctx, trial_steps, repeats, max_T, keep, scratch):
+    """The estimator-guided autotuner: returns (seconds per step of the
+    schedule kept, number of candidates timed)."""
+    best = ctypes.c_double()
+    n = ctypes.c_int32()
+    st = lib().wave_autotune_guided(ctx, trial_steps, repeats, max_T, keep, ctypes.c_void_p(scratch.data_ptr()),
+                                    scratch.numel() * scratch.element_size(), ctypes.byref(best), ctypes.byref(n))
+    _check(st, ctx)
+    return best.value, n.value
 
 
 def wave_batch(ctxs, nt, nsrc, src, wavelets, nrec, rec, rec_out, dobs, grad_m, ckpt_every, scratch):

@@ -95,7 +95,7 @@ def test_ab2_schedules_and_limits():
     from paper_1806_08299_amd import DiffOp, WaveError
     w, dt = _work((60, 40, 70), 4, 9, seed=81)
     op = _op(w, dt, time_tile=0)
-    assert op.schedule().T == 8 and op.schedule().slab == 48       # default at radius 2 in 3D
+    assert op.schedule().T == 16 and op.schedule().slab == 64      # default at radius 2 in 3D
     op8 = _op(wi.laplace(shape=(30, 30, 70), so=8, nt=3, seed=2), dt / 10.0, time_tile=0)
     assert op8.schedule().T == -1                                  # untiled beyond radius 2
     with pytest.raises(WaveError) as e:

@@ -1,0 +1,60 @@
+"""GPU tests of the autotuners (implementation chapter, "Auto-tuning";
+evaluation chapter, "Minimising runtime based on tile size choices").
+
+* the exhaustive tuner and the estimator-guided one both keep a schedule
+  whose result is bitwise that of the untiled sweep;
+* the guided tuner times fewer candidates than phase 1 of the exhaustive one
+  holds, and the schedule it keeps is close to the exhaustive winner's speed;
+* keep < 1 is refused.
+"""
+import numpy as np
+import pytest
+import torch
+
+from test_gpu_forward import _op, _run, _small
+
+pytestmark = pytest.mark.gpu
+
+
+def _seconds(op, w, reps=3):
+    wav = torch.from_numpy(w.wavelet).cuda()
+    op.forward(w.nt, w.src_xyz, wav, w.rec_xyz)
+    best = 1e30
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        op.forward(w.nt, w.src_xyz, wav, w.rec_xyz)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+@pytest.mark.parametrize("so", [2, 8])
+def test_guided_autotune_against_exhaustive(so):
+    from paper_1806_08299_amd import WaveError
+    from paper_1806_08299_amd.wave import tile_table, wave_autotune, wave_autotune_guided, wave_scratch_bytes, \
+        wave_tiled_max_depth
+    w = _small(so, (160, 176, 192), nbl=6, seed=400 + so, nt=32)
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    sc = op.scratch(wave_scratch_bytes(op.ctx, 16, 0, 0, 0, 0))
+    wave_autotune(op.ctx, 16, 2, 8, sc)
+    ex = op.schedule()
+    t_ex = _seconds(op, w)
+    rec_e, fin_e = _run(op, w)
+    assert np.array_equal(fin_e, fin_u) and np.array_equal(rec_e, rec_u)
+    sc = op.scratch(wave_scratch_bytes(op.ctx, 16, 0, 0, 0, 0))
+    _, timed = wave_autotune_guided(op.ctx, 16, 2, 8, 10, sc)
+    gd = op.schedule()
+    t_gd = _seconds(op, w)
+    rec_g, fin_g = _run(op, w)
+    assert np.array_equal(fin_g, fin_u) and np.array_equal(rec_g, rec_u)
+    phase1 = 1 + sum(wave_tiled_max_depth(so, 3, tile=t) for t in tile_table(3)) + 8
+    print("so %d: exhaustive %s %.3f ms, guided %s %.3f ms, %d timed (phase 1 holds %d)"
+          % (so, ex, t_ex, gd, t_gd, timed, phase1), flush=True)
+    assert timed < phase1 + 5 * 8          # fewer than phase 1 + the zchunk sweep of five
+    assert t_gd <= 1.25 * t_ex
+    with pytest.raises(WaveError):
+        wave_autotune_guided(op.ctx, 16, 2, 8, 0, sc)
