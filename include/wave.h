@@ -71,9 +71,10 @@ typedef struct wave_desc {
   double sigma_max;      /* damping maximum in 1/s (ignored if nbl == 0) */
   int32_t time_tile;     /* T >= 1 time steps per time tile; -1 = untiled single-step
                             sweep (the reference schedule); 0 = default: 3D T = 3 on
-                            32x64 tiles at radius 1; 2D T = 4 up to radius 2, T = 2 up
-                            to radius 4; untiled otherwise (the measured best on
-                            MI355X; wave_autotune refines by timing) */
+                            64x64 tiles at radius 1, T = 2 on 32x128 tiles at radius 2;
+                            2D T = 4 up to radius 2, T = 2 up to radius 4; untiled
+                            otherwise (the measured best on MI355X; wave_autotune
+                            refines by timing) */
   int32_t skew;          /* skewing factor: halo per fused step on the tiled axes (slab = 0)
                             or plane shift per step of the skewed schedule (slab > 0);
                             0 = r; must be >= r (background chapter, "Validity of skewing
@@ -95,7 +96,9 @@ typedef struct wave_desc {
                             0 = register-tiled or untiled sweep */
   int32_t zchunks;       /* segments of axis 0 per launch (of a slab, with slab > 0);
                             0 = auto (untiled 3D: about 32 workgroups per CU, segments of
-                            at least max(16, 4r) planes; time-tiled 2D: about 16 per CU) */
+                            at least max(16, 4r) planes; register-tiled 3D: the most
+                            segments whose workgroups fit one per CU; time-tiled 2D:
+                            about 16 per CU) */
 } wave_desc;
 
 typedef struct wave_ctx wave_ctx;

@@ -402,16 +402,24 @@ struct Plan {
 // Axis-0 segments when the caller gives none.  The untiled 3D sweep runs
 // best with segments of ~20-25 planes on MI355X (592^3: 24-32 segments
 // 298-299 Gpts/s, 12 segments 285), i.e. about 32 workgroups per CU; the
-// time-tiled sweeps want very different counts by depth and order, which
-// wave_autotune finds.
+// register-tiled wave sweeps with long segments, at most one workgroup per
+// CU (592^3: 64 x 64 at depth 3 and 32 x 128 at depth 2 best with 2
+// segments); wave_autotune refines.
 int auto_zchunks(const wave_ctx* c, int64_t base_blocks, int kind, int T, int64_t nz) {
   // time-tiled diffusion (one level per stage, fewer registers): ~6 per CU
   // (500^3, order 2, depth 4: 8 segments 1481 Gpts/s, 3 segments 1111).
   // 2D (a row of 1 x 1024 tiles per plane): ~16 per CU (16384^2 wave,
   // order 4, depth 4: 256 segments 643 Gpts/s against 469 with 31).
-  const int64_t tiled_per_cu = c->dim == 2 ? 16 : (c->eq == 1 ? 6 : 2);
+  const int64_t tiled_per_cu = c->dim == 2 ? 16 : (c->eq == 1 ? 6 : 1);
   const int64_t target = (kind == KIND_UNTILED) ? (c->dim == 3 ? 32LL : 8LL) * c->num_cu : tiled_per_cu * c->num_cu;
   int64_t zc = (target + base_blocks - 1) / base_blocks;
+  if (kind != KIND_UNTILED && c->dim == 3 && c->eq == 0) {
+    // one resident workgroup per CU, each a long segment: the most segments
+    // whose workgroups all run in the first wave (a second, partial wave of
+    // such workgroups leaves most CUs idle: 592^3 at radius 1, 121 tiles,
+    // 2 segments 400 Gpts/s against 329 with 3)
+    zc = std::max<int64_t>(1, target / base_blocks);
+  }
   // A segment re-reads 2R planes of window fill: keep it at least 4R long.
   const int64_t min_len = (kind == KIND_UNTILED) ? std::max<int64_t>(16, 4LL * c->R)
                                                  : std::max<int64_t>(16, 4LL * T * c->R);
@@ -1042,18 +1050,19 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
     return s;
   }
   if (T0 == -2) {
-    // Default schedule from measurements on MI355X (592^3, layered model):
-    // depth 3 on 32 x 64 tiles wins at radius 1 in 3D (1.36x); from radius 2
-    // on the time-tiled sweep wins only with a tuned segment count (radius
-    // 2) or not at all, so the untiled sweep is the default.  wave_autotune
-    // refines by timing on the actual problem.
-    // 2D (16384^2, 100 steps): depth 4 up to radius 2 (2.8x, 2.3x), depth
-    // 2 up to radius 4 (1.4x), untiled beyond.
+    // Default schedule from measurements on MI355X (592^3, layered model,
+    // about one workgroup per CU of axis-0 segments): depth 3 on 64 x 64
+    // tiles at radius 1 in 3D (1.38x the untiled sweep), depth 2 on 32 x 128
+    // tiles at radius 2 (1.28x); from radius 3 on no time-tiled schedule
+    // beats the untiled sweep, which is the default.  wave_autotune refines
+    // by timing on the actual problem.
+    // 2D (16384^2, 100 steps): depth 4 up to radius 2 (2.7x, 2.3x), depth
+    // 2 up to radius 4 (1.5x), untiled beyond.
     int best = -1;
-    const int Td = c->dim == 3 ? (c->R <= 1 ? 3 : 0) : (c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0));
+    const int Td = c->dim == 3 ? (c->R <= 1 ? 3 : (c->R == 2 ? 2 : 0)) : (c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0));
     if (Td > 0) {
       const int oshape = c->shape;
-      if (c->dim == 3 && shape0 == 0) c->shape = 2;
+      if (c->dim == 3 && shape0 == 0) c->shape = c->R <= 1 ? 1 : 3;
       Plan pl;
       if (make_plan(c, KIND_TILED, Td, pl) == WAVE_OK) best = Td;
       else c->shape = oshape;
