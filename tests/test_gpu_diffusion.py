@@ -15,6 +15,7 @@ import torch
 
 import oracle
 import waveinputs as wi
+from parity import assert_field
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +41,7 @@ def test_diffusion_against_oracle_3d(so):
     op = _op(w)
     got = op.forward(w.nt, torch.from_numpy(w.u0).cuda()).cpu().numpy().astype(np.float64)
     ref = _oracle(w, w.nt)
-    assert rel(got, ref) <= 1e-5
+    assert_field(got, ref, 1e-5)
 
 
 @pytest.mark.parametrize("so", [4, 16])
@@ -49,7 +50,7 @@ def test_diffusion_against_oracle_2d(so):
     print("diffusion 2D so%d" % so, flush=True)
     op = _op(w)
     got = op.forward(w.nt, torch.from_numpy(w.u0).cuda()).cpu().numpy().astype(np.float64)
-    assert rel(got, _oracle(w, w.nt)) <= 1e-5
+    assert_field(got, _oracle(w, w.nt), 1e-5)
 
 
 def _schedules(so, ndim):
@@ -104,7 +105,7 @@ def test_diffusion_edge_cases():
         t = wi.laplace(shape=shape, so=16, nt=7, seed=1)
         o = _op(t)
         got = o.forward(t.nt, torch.from_numpy(t.u0).cuda())
-        assert rel(got.cpu().numpy().astype(np.float64), _oracle(t, t.nt)) <= 1e-5, shape
+        assert_field(got.cpu().numpy(), _oracle(t, t.nt), 1e-5, str(shape))
         if len(shape) == 3:
             o.set_schedule(1, 0, 1, 0)
             assert torch.equal(o.forward(t.nt, torch.from_numpy(t.u0).cuda()), got)

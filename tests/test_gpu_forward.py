@@ -15,6 +15,7 @@ import torch
 
 import oracle
 import waveinputs as wi
+from parity import assert_field, assert_traces
 
 pytestmark = pytest.mark.gpu
 
@@ -85,8 +86,8 @@ def test_point_source_64_untiled_matches_oracle(ps64_ref):
     assert np.abs(fin).max() > 1e-3, "solution is (nearly) zero"
     assert np.all(np.isfinite(fin))
     for lev in (0, 1):
-        assert rel(fin[lev], ref["final"][lev]) <= TOL, lev
-    assert rel(rec, ref["rec"]) <= TOL
+        assert_field(fin[lev], ref["final"][lev], TOL, "level %d" % lev)
+    assert_traces(rec, ref["rec"], TOL)
 
 
 @pytest.mark.parametrize("T", [1, 2, 4])
@@ -100,7 +101,7 @@ def test_point_source_64_tiled_bitwise_equals_untiled(ps64_ref, T):
         rec_t, fin_t = _run(op, w)
         assert np.array_equal(fin_t, fin_u), (T, shape)
         assert np.array_equal(rec_t, rec_u), (T, shape)
-    assert rel(fin_t[0], ref["final"][0]) <= TOL
+    assert_field(fin_t[0], ref["final"][0], TOL)
 
 
 # --------------------------------------------------------------------------- every order
@@ -130,8 +131,8 @@ def test_every_order_3d_oracle_and_bitwise(so):
     ref = _oracle(w)
     op = _op(w, time_tile=-1)
     rec_u, fin_u = _run(op, w)
-    assert rel(fin_u[0], ref["final"][0]) <= TOL
-    assert rel(rec_u, ref["rec"]) <= TOL
+    assert_field(fin_u[0], ref["final"][0], TOL)
+    assert_traces(rec_u, ref["rec"], TOL)
     ran = 0
     for T, shp in _schedules(R, 3):
         if not _try_schedule(op, T, shp):
@@ -151,8 +152,8 @@ def test_every_order_2d_oracle_and_bitwise(so):
     ref = _oracle(w)
     op = _op(w, time_tile=-1)
     rec_u, fin_u = _run(op, w)
-    assert rel(fin_u[0], ref["final"][0]) <= TOL
-    assert rel(rec_u, ref["rec"]) <= TOL
+    assert_field(fin_u[0], ref["final"][0], TOL)
+    assert_traces(rec_u, ref["rec"], TOL)
     for T, shp in _schedules(R, 2):
         if not _try_schedule(op, T, shp):
             continue
@@ -180,7 +181,7 @@ def test_partial_windows_and_nt_edge_cases():
     rec_t, fin_t = _run(op, w)
     assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u)
     ref = _oracle(w)
-    assert rel(fin_u[0], ref["final"][0]) <= TOL
+    assert_field(fin_u[0], ref["final"][0], TOL)
     # nt = 0: final state is the (zero) initial state, no traces
     rec0, fin0 = _run(op, w, nt=0)
     assert np.array_equal(fin0, np.zeros_like(fin0))
@@ -201,9 +202,9 @@ def test_tiny_grid_and_points_on_boundary_or_outside():
     ref = _oracle(w)
     op = _op(w, time_tile=-1)
     rec_u, fin_u = _run(op, w)
-    assert rel(fin_u[0], ref["final"][0]) <= TOL
+    assert_field(fin_u[0], ref["final"][0], TOL)
     assert np.array_equal(rec_u[:, 1], np.zeros(12, np.float32))
-    assert rel(rec_u, ref["rec"]) <= TOL
+    assert_traces(rec_u, ref["rec"], TOL)
     for T, shp in _schedules(4, 3):
         if not _try_schedule(op, T, shp):
             continue
@@ -224,7 +225,7 @@ def test_initial_state_and_resume_bitwise():
     g = oracle.Grid(w.shape, w.spacing, w.dt, w.so, nbl=w.nbl, sigma_max=w.sigma_max)
     ref = oracle.forward(g, w.m.astype(np.float64), 20, w.src_xyz, w.wavelet.astype(np.float64), w.rec_xyz,
                          u_init=u0.cpu().numpy().astype(np.float64), want_final=True)
-    assert rel(fin_full.cpu().numpy()[0], ref["final"][0]) <= TOL
+    assert_field(fin_full.cpu().numpy()[0], ref["final"][0], TOL)
 
 
 def test_error_paths():
@@ -270,7 +271,8 @@ def test_empty_point_sets_and_degenerate_grids(shape):
     torch.cuda.synchronize()
     assert rec is None
     fin_u = fin.cpu().numpy()
-    assert rel(fin_u[0], ref["final"][0]) <= TOL and rel(fin_u[1], ref["final"][1]) <= TOL
+    assert_field(fin_u[0], ref["final"][0], TOL)
+    assert_field(fin_u[1], ref["final"][1], TOL)
     for T, shp in _schedules(2, nd):
         if not _try_schedule(op, T, shp):
             continue
@@ -330,8 +332,8 @@ def test_dense_receiver_lines_on_adjacent_rows(shape):
     ref = _oracle(w)
     op = _op(w, time_tile=-1)
     rec_u, fin_u = _run(op, w)
-    assert rel(fin_u[0], ref["final"][0]) <= TOL
-    assert rel(rec_u, ref["rec"]) <= TOL
+    assert_field(fin_u[0], ref["final"][0], TOL)
+    assert_traces(rec_u, ref["rec"], TOL)
     for T, shp in _schedules(2, nd):
         if not _try_schedule(op, T, shp):
             continue
