@@ -432,6 +432,26 @@ def batch_bench(args, dev, stream):
     finite = all(bool(torch.isfinite(g).all().item()) for g in grads)
     del G
     torch.cuda.empty_cache()
+    # the other branch layout: one graph branch for all radii in the forward
+    # (no side-by-side launches of different orders), one per radius in the
+    # gradient
+    os.environ["WAVE_BATCH_BRANCHES"] = "0"
+    try:
+        B1 = ShotBatch(ops, nt, [w.src_xyz for w in S], [w.rec_xyz for w in S])
+        timed(lambda: B1.run(wavs))
+        t_fwd1, (recs1, _) = timed(lambda: B1.run(wavs))
+        same1 = all(torch.equal(a, b) for a, b in zip(recs1, recs_seq))
+        del B1
+        torch.cuda.empty_cache()
+        os.environ["WAVE_BATCH_BRANCHES"] = "1"
+        G1 = ShotBatch(ops, nt, [w.src_xyz for w in S], [w.rec_xyz for w in S], ckpt_every=K, gradient=True)
+        timed(lambda: G1.run(wavs, dobs))
+        tg1, _ = timed(lambda: G1.run(wavs, dobs))
+        del G1
+        torch.cuda.empty_cache()
+    finally:
+        del os.environ["WAVE_BATCH_BRANCHES"]
+    log("batch, other branch layout: forward (one branch) %.3f s, gradient (a branch per radius) %.3f s" % (t_fwd1, tg1))
     log("batch: batched forward %.3f s (first call %.3f s), gradient %.3f s (first call %.3f s)"
         % (t_fwd, t_first, tg, tg_first))
     # algorithmic bytes: forward 16 B per point-update (20/T with a time
@@ -448,6 +468,11 @@ def batch_bench(args, dev, stream):
                         "gradient checkpoints every %d" % (len(S), round(min(w.npts for w in S) ** (1 / 3)),
                                                           round(max(w.npts for w in S) ** (1 / 3)), npts / 1e6, nt, K),
             "schedules": scheds, "unit": "Gpts/s",
+            "other_branch_layout": {"forward_one_branch": round(npts * nt / t_fwd1 / 1e9, 2),
+                                    "gradient_branch_per_radius": round(npts * nt / tg1 / 1e9, 2),
+                                    "bitwise_equal_to_sequential": same1,
+                                    "note": "the default is a graph branch per radius for the forward, one branch for "
+                                            "the gradient; here the other layout (WAVE_BATCH_BRANCHES=0, then =1)"},
             "forward": {"value": round(npts * nt / t_fwd / 1e9, 2), "s": round(t_fwd, 4),
                         "first_call_s": round(t_first, 4), "sequential_value": round(npts * nt / t_seq / 1e9, 2),
                         "speedup_vs_sequential": round(t_seq / t_fwd, 3), "bitwise_equal_to_sequential": same_fwd},

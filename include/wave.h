@@ -220,12 +220,17 @@ wave_status wave_adjoint_grad(wave_ctx* ctx, int32_t nt,
  * finding its shot from the launch arguments.  A gradient batch merges all
  * shots; a forward-only batch merges consecutive shots up to 96 MiB of
  * per-step working set and runs those groups one after another (cache
- * locality between steps).  The merged sequence is
+ * locality between steps).  In a forward-only batch the shots of each
+ * stencil radius form an independent branch of the captured graph (a stream
+ * each), so the launches of different orders run side by side; a gradient
+ * batch keeps one branch (measured faster).  The environment variable
+ * WAVE_BATCH_BRANCHES=0 or =1 forces one branch or one per radius.  The merged sequence is
  * captured into a HIP graph and launched; a later call with the same
  * arguments on contexts that no other call has touched since replays that
  * graph without recording again (device inputs may change in between).
  * Results are bitwise those of the per-shot calls.  Every shot's schedule
- * must be the untiled sweep or T <= 2 (WAVE_EUNSUPPORTED otherwise); a
+ * must be the untiled sweep, the skewed schedule, or a register-tiled depth
+ * T <= 2 on the 64x64 or 32x64 tile (WAVE_EUNSUPPORTED otherwise); a
  * context may appear once; calls on the same contexts must not overlap.
  * Errors: WAVE_EINVAL (null arrays, duplicate context, different streams),
  * WAVE_ENOMEM (scratch too small), WAVE_EHIP; the message is on ctxs[0]. */

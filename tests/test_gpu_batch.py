@@ -71,8 +71,12 @@ def _single_forward(S, sched, wav):
     return rec.cpu().numpy()
 
 
-def test_batch_forward_bitwise_equals_single_shots(shots):
+@pytest.mark.parametrize("branches", ["1", "0"])
+def test_batch_forward_bitwise_equals_single_shots(shots, branches, monkeypatch):
+    """Shots of different radii in independent graph branches (default) or
+    on one stream: bitwise the shots run alone either way."""
     from paper_1806_08299_amd import ShotBatch
+    monkeypatch.setenv("WAVE_BATCH_BRANCHES", branches)
     ops = [_op(S, SHOTS[i][2]) for i, S in enumerate(shots)]
     wavs = [torch.from_numpy(S["wav"]).cuda() for S in shots]
     B = ShotBatch(ops, NT, [S["src"] for S in shots], [S["rec"] for S in shots])
@@ -91,8 +95,10 @@ def test_batch_forward_bitwise_equals_single_shots(shots):
     assert np.linalg.norm(r - o["rec"]) / np.linalg.norm(o["rec"]) <= 1e-5
 
 
-def test_batch_gradient_bitwise_equals_single_shots(shots):
+@pytest.mark.parametrize("branches", ["1", "0"])
+def test_batch_gradient_bitwise_equals_single_shots(shots, branches, monkeypatch):
     from paper_1806_08299_amd import ShotBatch
+    monkeypatch.setenv("WAVE_BATCH_BRANCHES", branches)
     ops = [_op(S, SHOTS[i][2]) for i, S in enumerate(shots)]
     wavs = [torch.from_numpy(S["wav"]).cuda() for S in shots]
     rng = np.random.default_rng(7)
