@@ -135,10 +135,12 @@ def tune_untiled(op, trial_steps=40, repeats=2):
     return best[1]
 
 
-def autotune(op, trial_steps=40):
-    from paper_1806_08299_amd.wave import wave_autotune, wave_scratch_bytes
-    sc = op.scratch(wave_scratch_bytes(op.ctx, trial_steps, 0, 0, 0, 0))
-    return wave_autotune(op.ctx, trial_steps, 2, 8, sc)
+def autotune(op, w, trial_steps=40):
+    """The autotuner with trial forwards that carry the workload's source and
+    receivers."""
+    best = op.autotune(trial_steps, 2, 8, w.src_xyz, w.rec_xyz)
+    op._scratch = None
+    return best
 
 
 def guided_vs_exhaustive(op, w, wav, stream, trial_steps=40, keep=10):
@@ -146,19 +148,19 @@ def guided_vs_exhaustive(op, w, wav, stream, trial_steps=40, keep=10):
     context: candidates timed, tuning wall time, and the rate of each kept
     schedule over the full run."""
     import torch
-    from paper_1806_08299_amd.wave import wave_autotune, wave_autotune_guided, wave_scratch_bytes
+    from paper_1806_08299_amd.wave import wave_autotune_points, wave_autotune_scratch_bytes
     out = {}
-    sc = op.scratch(wave_scratch_bytes(op.ctx, trial_steps, 0, 0, 0, 0))
+    sc = op.scratch(wave_autotune_scratch_bytes(op.ctx, trial_steps, len(w.src_xyz), len(w.rec_xyz)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    wave_autotune(op.ctx, trial_steps, 2, 8, sc)
+    wave_autotune_points(op.ctx, trial_steps, 2, 8, 0, w.src_xyz, w.rec_xyz, sc)
     t_ex = time.perf_counter() - t0
     ex = op.schedule()
     out["exhaustive"] = {"schedule": sched_dict(ex), "tuning_s": round(t_ex, 2),
                          "value": round(_rate(op, w.nt, w, wav, stream, 1), 1)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, n = wave_autotune_guided(op.ctx, trial_steps, 2, 8, keep, sc)
+    _, n = wave_autotune_points(op.ctx, trial_steps, 2, 8, keep, w.src_xyz, w.rec_xyz, sc)
     t_gd = time.perf_counter() - t0
     gd = op.schedule()
     out["guided"] = {"schedule": sched_dict(gd), "tuning_s": round(t_gd, 2), "timed_candidates": n, "keep": keep,
@@ -300,7 +302,7 @@ def gradient_bench(args, dev, stream):
     op = WaveOp(init.shape, init.spacing, init.dt, init.so, torch.from_numpy(init.m).to(dev), nbl=init.nbl,
                 sigma_max=init.sigma_max, time_tile=-1)
     wv = torch.from_numpy(init.wavelet).to(dev)
-    autotune(op)
+    autotune(op, init)
     tuned = op.schedule()
     out = {"workload": "%s, model %s, nt=%d, checkpoints every %d"
                        % (init.name, "x".join(map(str, init.shape)), init.nt, K), "unit": "Gpts/s"}
@@ -330,7 +332,7 @@ def gradient_bench(args, dev, stream):
                 "grad_finite": bool(torch.isfinite(gm).all().item())})
     # Roofline of the two phases: algorithmic bytes of their sweeps (forward
     # 16 B or 20/T B per point-update; recompute storing the history + 4 B;
-    # adjoint with imaging + 12 B) over the phase's HIP-event time; the
+    # adjoint with imaging + 4 + 8/T B) over the phase's HIP-event time; the
     # per-kernel split is in profiles/gradient_kernels_const2000_256cube_so8.txt.
     T = tuned[0]
     b_f, b_h, b_a = (wave_bytes_per_point(T, md) for md in (0, 1, 2))
@@ -355,7 +357,63 @@ def gradient_bench(args, dev, stream):
         log("gradient untiled: fwd %.3f s + recompute/adjoint %.3f s" % (uf, ua))
     del op
     torch.cuda.empty_cache()
+    if not args.no_untiled:
+        out["by_order"] = gradient_orders(init, dev, stream, 200 if args.quick else 400, K)
     return out
+
+
+def gradient_orders(init, dev, stream, nt, K):
+    """The same gradient problem (model, geometry, dt) at space orders 2 and
+    4 over nt steps: the autotuned schedule against the untiled sweep.  The
+    time-tiled adjoint carries each point's imaging sum across its window in
+    registers, so the gradient is read and written once per window."""
+    import torch
+    from paper_1806_08299_amd import WaveOp
+    from paper_1806_08299_amd.wave import wave_bytes_per_point
+    wv = torch.from_numpy(np.ascontiguousarray(init.wavelet[:nt])).to(dev)
+    rows = []
+    for so in (2, 4):
+        op = WaveOp(init.shape, init.spacing, init.dt, so, torch.from_numpy(init.m).to(dev), nbl=init.nbl,
+                    sigma_max=init.sigma_max, time_tile=-1)
+        rec0, _ = op.forward(nt, init.src_xyz, wv, init.rec_xyz)
+        resid = rec0.clone()
+
+        def one(sched):
+            op.set_schedule(*sched)
+            best, gm = None, None
+            for _ in range(2):
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                torch.cuda.synchronize()
+                e0.record(stream)
+                op.forward(nt, init.src_xyz, wv, init.rec_xyz, ckpt_every=K, adjoint_scratch=True)
+                e1.record(stream)
+                gm, _ = op.adjoint_grad(nt, init.src_xyz, wv, init.rec_xyz, resid, K, reuse=True)
+                e2.record(stream)
+                torch.cuda.synchronize()
+                t = (e0.elapsed_time(e1) * 1e-3, e1.elapsed_time(e2) * 1e-3)
+                if best is None or sum(t) < sum(best):
+                    best = t
+            return best, gm.cpu()
+
+        (uf, ua), gu = one((-1, 0, 0, 0))
+        autotune(op, init)
+        tuned = op.schedule()
+        (tf, ta), gt = one(tuned)
+        T = tuned[0]
+        rows.append({"space_order": so, "nt": nt, "schedule": sched_dict(tuned),
+                     "value": round(init.npts * nt / (tf + ta) / 1e9, 2),
+                     "untiled_value": round(init.npts * nt / (uf + ua) / 1e9, 2),
+                     "speedup_vs_untiled": round((uf + ua) / (tf + ta), 3),
+                     "adjoint_speedup_vs_untiled": round(ua / ta, 3),
+                     "adjoint_bytes_per_point_update": wave_bytes_per_point(T, 2),
+                     "bitwise_equal_to_untiled": bool(torch.equal(gt, gu)),
+                     "forward_with_checkpoints_s": round(tf, 4), "recompute_plus_adjoint_s": round(ta, 4),
+                     "untiled_forward_s": round(uf, 4), "untiled_recompute_plus_adjoint_s": round(ua, 4)})
+        log("gradient so%d: %s fwd %.3f + adj %.3f s, untiled %.3f + %.3f s (%.2fx)"
+            % (so, tuned, tf, ta, uf, ua, (uf + ua) / (tf + ta)))
+        del op
+        torch.cuda.empty_cache()
+    return rows
 
 
 def batch_bench(args, dev, stream):
@@ -365,7 +423,7 @@ def batch_bench(args, dev, stream):
     import torch
     import waveinputs as wi
     from paper_1806_08299_amd import ShotBatch, WaveOp
-    from paper_1806_08299_amd.wave import wave_autotune, wave_bytes_per_point, wave_scratch_bytes
+    from paper_1806_08299_amd.wave import wave_bytes_per_point
     if args.quick:
         S = wi.shot_batch(nshots=6, nt=100, sizes=[(64 + 16 * (i % 3), 64, 80) for i in range(6)], workers=8)
     else:
@@ -376,10 +434,9 @@ def batch_bench(args, dev, stream):
     for w in S:
         op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
                     sigma_max=w.sigma_max, time_tile=-1)
-        sc = op.scratch(wave_scratch_bytes(op.ctx, 20, 0, 0, 0, 0))
-        wave_autotune(op.ctx, 20, 1, 16, sc)
+        op.autotune(20, 1, 16, w.src_xyz, w.rec_xyz)
         if op.schedule().T > 2 and op.schedule().slab == 0:   # batched register tiles: T <= 2
-            wave_autotune(op.ctx, 20, 1, 2, sc)
+            op.autotune(20, 1, 2, w.src_xyz, w.rec_xyz)
         op._scratch = None
         ops.append(op)
         wavs.append(torch.from_numpy(w.wavelet).to(dev))
@@ -415,7 +472,9 @@ def batch_bench(args, dev, stream):
             torch.cuda.empty_cache()
             out.append(gm)
         return out
-    tg_seq, _ = timed(seq_grad)
+    # best of two calls (the first gradient calls of a process ran up to 7 %
+    # slower, batched and sequential alike)
+    tg_seq = min(timed(seq_grad)[0] for _ in range(2))
     torch.cuda.empty_cache()
     log("batch: %d shots, %.1f Mpts, sequential forward %.3f s, gradient %.3f s" % (len(S), npts / 1e6, t_seq, tg_seq))
 
@@ -429,6 +488,7 @@ def batch_bench(args, dev, stream):
     G = ShotBatch(ops, nt, [w.src_xyz for w in S], [w.rec_xyz for w in S], ckpt_every=K, gradient=True)
     tg_first, _ = timed(lambda: G.run(wavs, dobs))
     tg, (_, grads) = timed(lambda: G.run(wavs, dobs))
+    tg = min(tg, timed(lambda: G.run(wavs, dobs))[0])
     finite = all(bool(torch.isfinite(g).all().item()) for g in grads)
     del G
     torch.cuda.empty_cache()
@@ -446,7 +506,7 @@ def batch_bench(args, dev, stream):
         os.environ["WAVE_BATCH_BRANCHES"] = "1"
         G1 = ShotBatch(ops, nt, [w.src_xyz for w in S], [w.rec_xyz for w in S], ckpt_every=K, gradient=True)
         timed(lambda: G1.run(wavs, dobs))
-        tg1, _ = timed(lambda: G1.run(wavs, dobs))
+        tg1 = min(timed(lambda: G1.run(wavs, dobs))[0] for _ in range(2))
         del G1
         torch.cuda.empty_cache()
     finally:
@@ -515,7 +575,7 @@ def _rate(op, nt, w, wav, stream, reps=2, sched=None):
             op.set_schedule(*sched[:4], tile=sched[4], slab=sched[5])
         except WaveError:
             return 0.0
-    op.forward(nt, w.src_xyz, wav, w.rec_xyz)
+    op.forward(min(nt, 20), w.src_xyz, wav[:min(nt, 20)].contiguous(), w.rec_xyz)   # warm-up
     best = 1e30
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -613,7 +673,7 @@ def c3_bench(dev, stream, quick=False):
     import torch
     import waveinputs as wi
     from paper_1806_08299_amd import WaveOp
-    from paper_1806_08299_amd.wave import Schedule, tile_table, wave_scratch_bytes, wave_tiled_max_depth
+    from paper_1806_08299_amd.wave import Schedule, tile_table, wave_tiled_max_depth
     n, nt = (160, 60) if quick else (768, 500)
     t0 = time.time()
     base = wi.smooth_768(so=12, nt=nt, n=n, device=dev)
@@ -625,16 +685,13 @@ def c3_bench(dev, stream, quick=False):
                         base.sigma_max, base.m, base.src_xyz, base.wavelet, base.rec_xyz)
         wav = torch.from_numpy(w.wavelet).to(dev)
         op = WaveOp(w.shape, w.spacing, w.dt, so, m, nbl=w.nbl, sigma_max=w.sigma_max, time_tile=-1)
-        from paper_1806_08299_amd.wave import wave_autotune
-        sc = op.scratch(wave_scratch_bytes(op.ctx, 16, 0, 0, 0, 0))
-        wave_autotune(op.ctx, 16, 1, 8, sc)
+        op.autotune(16, 1, 8, w.src_xyz, w.rec_xyz)
         op._scratch = None
         tuned = op.schedule()
         v_t = _rate(op, nt, w, wav, stream, 1)
-        untiled = max((_rate(op, nt, w, wav, stream, 1, Schedule(-1, 0, 0, zc, (0, 0), 0)), zc) for zc in (0, 24))
-        cands = [Schedule(T, 0, i + 1, 16, t, 0) for i, t in enumerate(tile_table(3))
-                 for T in range(1, wave_tiled_max_depth(so, 3, tile=t) + 1)]
-        cands += [Schedule(T, 0, 0, 2, (0, 0), Z) for T in (4, 8) for Z in (48, 64)]
+        untiled = max((_rate(op, nt, w, wav, stream, 1, Schedule(-1, 0, 0, zc, (0, 0), 0)), zc) for zc in (12,))
+        # the time-tiled schedules that came closest on the 592^3 workload
+        cands = [Schedule(1, 0, 3, 2, (32, 128), 0), Schedule(8, 0, 0, 2, (0, 0), 64), Schedule(4, 0, 0, 2, (0, 0), 64)]
         if tuned[0] >= 1:
             cands = [tuned]
         best = max((_rate(op, nt, w, wav, stream, 1, c), c) for c in cands)
@@ -717,7 +774,7 @@ def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16
     """The Laplace-operator workload (explicit diffusion) on the paper's grids
     (500^3 x 32 steps, 600^3 x 16 steps) at space orders 2..16: the default
     schedule, the best untiled and the best time-tiled schedule (minimum of
-    five runs each), and the algorithmic HBM rate of each (8/T B per
+    three runs each), and the algorithmic HBM rate of each (8/T B per
     point-update)."""
     import torch
     import waveinputs as wi
@@ -742,7 +799,7 @@ def laplace_bench(dev, stream, grids=((500, 32), (600, 16)), orders=(2, 4, 8, 16
                     return 0.0
                 op.forward(nt, u0, res)
                 ts = []
-                for _ in range(5):
+                for _ in range(3):
                     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                     torch.cuda.synchronize()
                     e0.record(stream)
@@ -911,7 +968,7 @@ def main():
     if args.T != 0:
         op.set_schedule(args.T, 0, args.shape if args.slab == 0 else 0, args.zchunks, slab=args.slab)
     else:
-        best = autotune(op)
+        best = autotune(op, w)
         log("autotune -> schedule %s, %.3f ms/step" % (op.schedule(), best * 1e3))
     sched = op.schedule()
     T = sched[0]

@@ -223,7 +223,7 @@ wave_status wave_adjoint_grad(wave_ctx* ctx, int32_t nt,
  * locality between steps).  In a forward-only batch the shots of each
  * stencil radius form an independent branch of the captured graph (a stream
  * each), so the launches of different orders run side by side; a gradient
- * batch keeps one branch (measured faster).  The environment variable
+ * batch keeps one branch (measured faster or level).  The environment variable
  * WAVE_BATCH_BRANCHES=0 or =1 forces one branch or one per radius.  The merged sequence is
  * captured into a HIP graph and launched; a later call with the same
  * arguments on contexts that no other call has touched since replays that
@@ -248,13 +248,15 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
  * every built depth T <= max_T, and the skewed schedule at T = 2, 4, ... <=
  * max_T (16 if max_T = 0) on slabs of 32 and 64 planes, all at the default
  * number of axis-0 segments.  Phase 2: 1..32 axis-0 segments for the five
- * fastest.  Phase 3: the skewing factor (r, a multiple of 4, 2r) of the best
+ * fastest and for the untiled sweep.  Phase 3: the skewing factor (r, a multiple of 4, 2r) of the best
  * register-tiled schedule, or the slab thickness and depth of the best skewed
  * one (the paper's skew experiment, "Effect of the skewing factor").  Keeps
- * the fastest.  Synchronises; needs scratch for `trial_steps` forward steps
- * without sources (wave_scratch_bytes(ctx, trial_steps, 0, 0, 0, 0)).  On a
- * diffusion context (diff_init) the trials are diff_forward calls from a zero
- * field between two levels in the scratch (2 N floats, also what
+ * the fastest; a time-tiled schedule replaces the untiled sweep only when
+ * faster by more than 1 % (the trials' run-to-run spread).  Synchronises;
+ * needs scratch for `trial_steps` forward steps without sources
+ * (wave_scratch_bytes(ctx, trial_steps, 0, 0, 0, 0)).  On a diffusion
+ * context (diff_init) the trials are diff_forward calls from a zero field
+ * between two levels in the scratch (2 N floats, also what
  * wave_scratch_bytes returns for such a context). */
 wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
                           void* scratch_dev, size_t scratch_bytes, double* best_seconds_per_step);
@@ -271,11 +273,35 @@ wave_status wave_autotune(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, i
  * compute side (the redundant work of a register tile x the register
  * anchors' cost interpolated in T, or the single-step kernel's) -- and times only the
  * `keep` >= 1 candidates the model ranks fastest; phase 2 then covers the two
- * fastest, phase 3 as in wave_autotune.  *timed_trials (may be NULL) receives
+ * fastest and the untiled sweep, phase 3 as in wave_autotune.  *timed_trials (may be NULL) receives
  * the number of candidates timed.  Arguments and errors as wave_autotune. */
 wave_status wave_autotune_guided(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
                                  int32_t keep, void* scratch_dev, size_t scratch_bytes,
                                  double* best_seconds_per_step, int32_t* timed_trials);
+
+/* The autotuner with the operator's point sets, since the paper's auto-tuner
+ * times the operator as it will run (implementation chapter, "Auto-tuning").
+ * The trial forwards of wave_autotune (keep = 0) or wave_autotune_guided
+ * (keep >= 1) carry the nsrc sources (a zero wavelet: their forcing lookups,
+ * not their values, cost time) and the nrec receivers at src_xyz / rec_xyz
+ * (host, [n][ndim] in the units of the spacing, as wave_forward).  Point
+ * lookups run on the planes that hold points in every workgroup that
+ * crosses them, so they cost a schedule with few long-running workgroups
+ * more than one with many short ones: a 512-receiver line costs a one-wave
+ * register-tiled sweep of 592^3 about 2 % per step, the untiled sweep 0.3 %.
+ * Scratch: wave_autotune_scratch_bytes(ctx, trial_steps, nsrc, nrec)
+ * (device).  A diffusion context takes no points (WAVE_EINVAL if nsrc or
+ * nrec > 0).  Other arguments and errors as wave_autotune_guided; keep = 0
+ * is accepted here and means exhaustive. */
+wave_status wave_autotune_points(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
+                                 int32_t keep, int32_t nsrc, const double* src_xyz, int32_t nrec,
+                                 const double* rec_xyz, void* scratch_dev, size_t scratch_bytes,
+                                 double* best_seconds_per_step, int32_t* timed_trials);
+
+/* Scratch bytes wave_autotune_points needs for these point counts (with
+ * nsrc = nrec = 0 also what wave_autotune and wave_autotune_guided need);
+ * 0 for a null context or invalid counts.  Host-only. */
+size_t wave_autotune_scratch_bytes(const wave_ctx* ctx, int32_t trial_steps, int32_t nsrc, int32_t nrec);
 
 /* Arithmetic-intensity estimators of the evaluation chapter ("Arithmetic
  * intensity under time-tiling").  Host-only, no device access.
@@ -313,8 +339,9 @@ wave_status wave_tile_extent(int32_t ndim, int32_t index, int32_t* ey, int32_t* 
  * schedule of depth time_tile (T = -1 untiled; damping computed from
  * indices; the register-tiled and the skewed schedules move the same
  * compulsory bytes) for mode 0 (forward), 1 (forward storing the history,
- * +4 B), 2 (adjoint reading the history and updating the gradient at every
- * stage, +12 B), 3 (explicit diffusion: read one level, write one level per
+ * +4 B), 2 (adjoint reading the history at every step and the gradient
+ * once per window, updating it in registers across the window's stages:
+ * +4 + 8/T B, i.e. (7 + T) 4 / T for T >= 2), 3 (explicit diffusion: read one level, write one level per
  * launch, 8/T B) or 4 (the two-level diffusion step: 12 B untiled, 16/T B
  * per time tile).  Host-only. */
 double wave_flops_per_point(int32_t ndim, int32_t space_order, int32_t damped);

@@ -1355,8 +1355,9 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt, const 
   // One graph branch per radius for a forward-only batch (32 shots of orders
   // 4 and 8: 1.02x against 0.995x the shots one by one on a single branch);
   // one branch for a gradient batch, where merging all shots in lockstep
-  // pays more (71.7 against 70.4 Gpts/s).  WAVE_BATCH_BRANCHES=0 / =1 forces
-  // one branch / one per radius.
+  // paid more before the adjoint fetched its history and gradient ahead
+  // (71.7 against 70.4 Gpts/s) and measures level since (3.850 against
+  // 3.853 s).  WAVE_BATCH_BRANCHES=0 / =1 forces one branch / one per radius.
   const char* env_b = std::getenv("WAVE_BATCH_BRANCHES");
   const bool use_branches = env_b && env_b[0] ? env_b[0] != '0' : !grad;
   auto signature = [&]() {
@@ -1579,20 +1580,41 @@ CandModel cand_model(wave_ctx* c, const Cand& k) {
   return M;
 }
 
-wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, int keep, void* scratch,
-                          size_t scratch_bytes, double* best, int* timed_count) {
+// Scratch of the autotuner's trials: wave_forward's layout for trial_steps
+// steps with the given point sets, then a wavelet of zeros [steps][nsrc] and
+// the receiver samples [steps][nrec]; diffusion: two levels.
+size_t autotune_bytes(const wave_ctx* c, int trial_steps, int nsrc, int nrec) {
+  if (c->eq != 0) return 2 * align_up(sizeof(float) * c->N);
+  return layout(c, trial_steps, nsrc, nrec, 0, 0).total + align_up(sizeof(float) * (size_t)trial_steps * nsrc) +
+         align_up(sizeof(float) * (size_t)trial_steps * nrec);
+}
+
+wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, int keep, int nsrc, const double* src,
+                          int nrec, const double* rec, void* scratch, size_t scratch_bytes, double* best,
+                          int* timed_count) {
   if (!c || trial_steps < 1 || repeats < 1 || keep < 0) return WAVE_EINVAL;
-  // Wave equation: trial forwards with the scratch layout of wave_forward.
-  // Diffusion: trial diff_forward calls from a zero field in the first half
-  // of the scratch into its second half.
+  // Wave equation: trial forwards with the scratch layout of wave_forward,
+  // carrying the operator's sources (a zero wavelet) and receivers, whose
+  // lookups cost the schedules differently.  Diffusion: trial diff_forward
+  // calls from a zero field in the first half of the scratch into its
+  // second half.
   const bool diff = c->eq != 0;
-  const Layout L = diff ? Layout{} : layout(c, trial_steps, 0, 0, 0, 0);
+  if (diff && (nsrc > 0 || nrec > 0)) return fail(c, WAVE_EINVAL, "a diffusion context has no sources or receivers");
+  wave_status vs;
+  if ((vs = validate_coords(c, nsrc, src)) || (vs = validate_coords(c, nrec, rec))) return vs;
+  const Layout L = diff ? Layout{} : layout(c, trial_steps, nsrc, nrec, 0, 0);
   const size_t level = align_up(sizeof(float) * c->N);
-  if (!scratch || scratch_bytes < (diff ? 2 * level : L.total)) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  if (!scratch || scratch_bytes < autotune_bytes(c, trial_steps, nsrc, nrec))
+    return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  float* twav = diff ? nullptr : (float*)((char*)scratch + L.total);
+  float* trec = diff ? nullptr : (float*)((char*)scratch + L.total + align_up(sizeof(float) * (size_t)trial_steps * nsrc));
   c->gen++;
   c->ck.valid = false;   // the trial sweeps overwrite the state (and perhaps the scratch)
   if (diff) {
     wave_status fs = fill(c, (float*)scratch, c->N, 0.0f);
+    if (fs != WAVE_OK) return fs;
+  } else if (nsrc > 0) {
+    wave_status fs = fill(c, twav, (int64_t)trial_steps * nsrc, 0.0f);
     if (fs != WAVE_OK) return fs;
   }
   std::vector<Cand> cands;
@@ -1622,8 +1644,8 @@ wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, 
       hipEventRecord(e0, c->stream);
       const wave_status st =
           diff ? diff_forward(c, trial_steps, (const float*)scratch, (float*)((char*)scratch + level))
-               : forward_core(c, trial_steps, 0, nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0,
-                              (char*)scratch, L);
+               : forward_core(c, trial_steps, nsrc, src, twav, nrec, rec, nrec > 0 ? trec : nullptr, nullptr,
+                              nullptr, 0, (char*)scratch, L);
       if (st != WAVE_OK) return 1e300;
       hipEventRecord(e1, c->stream);
       if (hipEventSynchronize(e1) != hipSuccess) return 1e300;
@@ -1698,8 +1720,14 @@ wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, 
   std::stable_sort(timed.begin(), timed.end(), better);
   double best_t = timed.empty() ? 1e300 : timed[0].first;
   Cand bc = timed.empty() ? Cand{oT, os, osh, osl, oz} : timed[0].second;
+  // the fastest untiled timing, for the final choice below
+  double best_untiled = 1e300;
+  Cand bu = cands[0];
+  for (const auto& tk : timed)
+    if (tk.second.T < 0 && tk.first < best_untiled) { best_untiled = tk.first; bu = tk.second; }
   auto consider = [&](const Cand& k) {
     const double t = timed_one(k);
+    if (k.T < 0 && t < best_untiled) { best_untiled = t; bu = k; }
     if (t < best_t) {
       best_t = t;
       bc = k;
@@ -1708,17 +1736,24 @@ wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, 
   // Phase 2: the number of axis-0 segments (grid size against per-workgroup
   // pipeline fill) for the five fastest schedules: at low orders a time-tiled
   // schedule that phase 1 ranks behind the untiled sweep can overtake it
-  // with more segments.
+  // with more segments.  The untiled sweep is always among them: it is the
+  // reference of the final choice below.
   const int zcs[8] = {1, 2, 4, 8, 12, 16, 24, 32};
+  std::vector<Cand> seg;
   for (size_t t = 0; t < std::min<size_t>(keep == 0 ? 5 : 2, timed.size()); ++t) {
     if (timed[t].first >= 1e300) break;
+    seg.push_back(timed[t].second);
+  }
+  bool has_untiled = false;
+  for (const Cand& k : seg) has_untiled |= k.T < 0;
+  if (!has_untiled && best_untiled < 1e300) seg.push_back(bu);
+  for (const Cand& b : seg)
     for (int z : zcs) {
       if (z > c->n0) break;
-      Cand k = timed[t].second;
+      Cand k = b;
       k.zc = z;
       consider(k);
     }
-  }
   // Phase 3: the skewing factor of the best register-tiled schedule (the
   // minimum legal skew r, a multiple of four, twice r), or the slab
   // thickness and depth of the best skewed schedule.
@@ -1746,6 +1781,13 @@ wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, 
       consider(k);
     }
   }
+  // A time-tiled schedule replaces the untiled sweep only when it is faster
+  // by more than the trials' run-to-run spread (1 %): at a tie the reference
+  // schedule is kept.
+  if (bc.T >= 1 && best_untiled < 1e300 && best_t > 0.99 * best_untiled) {
+    bc = bu;
+    best_t = best_untiled;
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   c->err.clear();
@@ -1765,14 +1807,32 @@ extern "C" {
 
 wave_status wave_autotune(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, void* scratch,
                           size_t scratch_bytes, double* best) {
-  return autotune_impl(c, trial_steps, repeats, max_T, 0, scratch, scratch_bytes, best, nullptr);
+  return autotune_impl(c, trial_steps, repeats, max_T, 0, 0, nullptr, 0, nullptr, scratch, scratch_bytes, best,
+                       nullptr);
 }
 
 wave_status wave_autotune_guided(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, int32_t keep,
                                  void* scratch, size_t scratch_bytes, double* best, int32_t* timed) {
   if (keep < 1) return c ? fail(c, WAVE_EINVAL, "keep must be >= 1") : WAVE_EINVAL;
   int n = 0;
-  const wave_status s = autotune_impl(c, trial_steps, repeats, max_T, keep, scratch, scratch_bytes, best, &n);
+  const wave_status s =
+      autotune_impl(c, trial_steps, repeats, max_T, keep, 0, nullptr, 0, nullptr, scratch, scratch_bytes, best, &n);
+  if (timed) *timed = n;
+  return s;
+}
+
+size_t wave_autotune_scratch_bytes(const wave_ctx* c, int32_t trial_steps, int32_t nsrc, int32_t nrec) {
+  if (!c || trial_steps < 1 || nsrc < 0 || nrec < 0) return 0;
+  return autotune_bytes(c, trial_steps, nsrc, nrec);
+}
+
+wave_status wave_autotune_points(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, int32_t keep,
+                                 int32_t nsrc, const double* src_xyz, int32_t nrec, const double* rec_xyz,
+                                 void* scratch, size_t scratch_bytes, double* best, int32_t* timed) {
+  if (c && (nsrc < 0 || nrec < 0)) return fail(c, WAVE_EINVAL, "negative point count");
+  int n = 0;
+  const wave_status s = autotune_impl(c, trial_steps, repeats, max_T, keep, nsrc, src_xyz, nrec, rec_xyz, scratch,
+                                      scratch_bytes, best, &n);
   if (timed) *timed = n;
   return s;
 }
@@ -1835,14 +1895,14 @@ double wave_flops_per_point(int32_t ndim, int32_t so, int32_t damped) {
 double wave_bytes_per_point(int32_t T, int32_t mode) {
   // compulsory traffic per point-update: read u^n, u^{n-1}, b once per launch,
   // write one level (in place, T <= 1) or two levels (ping-pong, T >= 2);
-  // history +4 B (write or read); imaging gradient +8 B (read-modify-write
-  // at every stage of the window).
+  // history +4 B (write or read, one level per step); imaging gradient read
+  // and written once per window, +8/T B.
   const double Tt = T < 1 ? 1.0 : (double)T;
   if (mode == 3) return 8.0 / Tt;   // diffusion: read u^n, write u^{n+T}
   if (mode == 4) return T <= 1 ? 12.0 : 16.0 / Tt;   // two-level: read 2 levels, write 1 (2 per time tile)
   double base = (T <= 1) ? 16.0 : 20.0 / Tt;
   if (mode == 1) base += 4.0;
-  if (mode == 2) base += 4.0 + 8.0;
+  if (mode == 2) base += 4.0 + 8.0 / Tt;
   return base;
 }
 

@@ -50,7 +50,8 @@
 // past the descriptor without wrapping 32 bits: loads return 0 (the zero
 // boundary values) and stores are dropped, with no branches and no 64-bit
 // address arithmetic in the loop.  Every load is issued one plane ahead of its
-// use.  Because b = dt^2/m also reads as 0 outside the grid, the update there
+// use (the tiled adjoint's history and gradient loads: at the start of the
+// iteration that uses them).  Because b = dt^2/m also reads as 0 outside the grid, the update there
 // evaluates to exactly +0 with no select.
 #pragma once
 #include <utility>
@@ -322,6 +323,15 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
   // AB: pc/pb hold u^n/u^{n-1} of the plane entering the window, pp u^n of
   // the plane being updated, ph/ph2 u^n/u^{n-1} of its halo.
   float pc[NP][RY], pp[NP][RY], pb[NP][RY], ph[NP][HPT], ph2[AB ? NP : 1][AB ? HPT : 1];
+  // history / gradient: one time level per launch; the adjoint's u and g of
+  // a plane are fetched with its other loads, NP planes ahead of their use
+  const int step = A.step0;
+  const int64_t N = (int64_t)n0 * A.s0;
+  constexpr bool HIST = (MODE == MODE_HIST || MODE == MODE_ADJ);
+  constexpr bool ADJ = (MODE == MODE_ADJ);
+  const rsrc_t rh = HIST ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ro;
+  const rsrc_t rg = ADJ ? sg.rsrc(A.grad) : ro;
+  float pu[ADJ ? NP : 1][ADJ ? RY : 1], pg[ADJ ? NP : 1][ADJ ? RY : 1];
   {
 #pragma unroll
     for (int j = 1; j <= 2 * R; ++j) {   // planes za-R .. za+R-1: logical 0..2R-1 at rotation 1
@@ -344,17 +354,19 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
         ph[q][h] = bload(rc, hcol[h], s1);
         if constexpr (AB) ph2[q][h] = bload(rp, hcol[h], s1);
       }
+      if constexpr (ADJ) {
+        const uint32_t sw = sg.off(za + q, za, zb);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+          pu[q][i] = bload(rh, col[i], sw);
+          pg[q][i] = bload(rg, col[i], sw);
+        }
+      }
     }
 #pragma unroll
     for (int i = 0; i < RY; ++i) zw[i][0] = 0.0f;
   }
 
-  const int step = A.step0;
-  const int64_t N = (int64_t)n0 * A.s0;
-  // history / gradient: one time level per launch
-  constexpr bool HIST = (MODE == MODE_HIST || MODE == MODE_ADJ);
-  const rsrc_t rh = HIST ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ro;
-  const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ro;
   const int nit = zb - za;
   // One plane; `rot` is the rotation after this iteration's push, `q` the
   // prefetch set holding this plane's loads.
@@ -362,12 +374,16 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
     constexpr int rot = decltype(rotc)::value;
     constexpr int q = decltype(qc)::value;
     __builtin_amdgcn_sched_barrier(0);   // keep unrolled copies from overlapping (register pressure)
-    float up[RY], bb[RY], hv[HPT];
+    float up[RY], bb[RY], hv[HPT], uu[ADJ ? RY : 1], gg[ADJ ? RY : 1];
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       zw[i][(2 * R + rot) % W] = AB ? ab2_input(pc[q][i], pb[q][i]) : pc[q][i];
       up[i] = pp[q][i];
       bb[i] = pb[q][i];
+      if constexpr (ADJ) {
+        uu[i] = pu[q][i];
+        gg[i] = pg[q][i];
+      }
     }
 #pragma unroll
     for (int h = 0; h < HPT; ++h) hv[h] = AB ? ab2_input(ph[q][h], ph2[AB ? q : 0][AB ? h : 0]) : ph[q][h];
@@ -388,6 +404,14 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
       for (int h = 0; h < HPT; ++h) {
         ph[q][h] = bload(rc, hcol[h], s1);
         if constexpr (AB) ph2[q][h] = bload(rp, hcol[h], s1);
+      }
+      if constexpr (ADJ) {
+        const uint32_t sw = sg.off(z + NP, za, zb);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+          pu[q][i] = bload(rh, col[i], sw);
+          pg[q][i] = bload(rg, col[i], sw);
+        }
       }
     }
     float* buf = lds + (z & 1) * PLB;
@@ -458,9 +482,8 @@ __global__ __launch_bounds__(64 * NW) void k_untiled(typename LaunchArgs<BATCH>:
         bstore(ro, o, so, v[i]);
         if (MODE == MODE_HIST) {
           bstore(rh, o, so, v[i]);
-        } else if (MODE == MODE_ADJ) {
-          const float u = bload(rh, o, so);
-          bstore(rg, o, so, image_step(bload(rg, o, so), u, st[i], v[i], zw[i][(R + rot) % W], up[i]));
+        } else if constexpr (ADJ) {
+          bstore(rg, o, so, image_step(gg[i], uu[i], st[i], v[i], zw[i][(R + rot) % W], up[i]));
         }
       }
       if (EV && sz) sample_rows<RY, HY>(A, z, ybase, xbase, lane, step, v, [&](int i) { return col[i] != kOOB; });
@@ -587,6 +610,38 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
 
   const int zs = za - T * R;   // first plane loaded
   const int nit = zb - za + 2 * T * R;
+  const int64_t N = (int64_t)n0 * A.s0;
+  // Adjoint imaging over the window: stage k's gradient term for a core
+  // point is added to the running value that stage k-1 produced R
+  // iterations earlier (the point's plane reaches stage k R planes later),
+  // so grad is read once (by stage 1) and written once (by stage T) per
+  // window, the terms summed in the per-step order of the single-step
+  // sweep.  ocol: core columns (kOOB elsewhere); gq[k-1]: stage k's running
+  // values of the last R iterations, oldest first.  An iteration issues its
+  // history and gradient loads at its start and uses them after its
+  // updates (a prefetch one iteration ahead measured slower: its second set
+  // of registers spills at the deeper tiles).
+  constexpr bool ADJ = (MODE == MODE_ADJ);
+  constexpr int TQ = (ADJ && T > 1) ? T - 1 : 1;
+  constexpr int RQ = (ADJ && T > 1) ? R : 1;
+  uint32_t ocol[ADJ ? RY : 1];
+  float gq[TQ][RQ][ADJ ? RY : 1];
+  const rsrc_t rg = ADJ ? sg.rsrc(A.grad) : ra;
+  auto hist_rsrc = [&](int k) { return sg.rsrc(A.hist + (int64_t)(stage_step(A, k) + 1 - A.hist_base) * N); };
+  if constexpr (ADJ) {
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+      const int ly = HY ? wrow0 + i : 0;
+      const bool rcore = !HY || (ly >= HYH && ly < HYH + CY);
+      ocol[i] = (rcore && xcore[HY ? 0 : i]) ? col[i] : kOOB;
+    }
+#pragma unroll
+    for (int k = 0; k < TQ; ++k)
+#pragma unroll
+      for (int j = 0; j < RQ; ++j)
+#pragma unroll
+        for (int i = 0; i < RY; ++i) gq[k][j][i] = 0.0f;
+  }
   float pc[RY], pp[RY], pb[T][RY];   // next iteration's loads
   {
     const uint32_t sc = sg.off(zs), sp = sg.off(zs - R);
@@ -604,18 +659,41 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
   }
   __syncthreads();
 
-  const int64_t N = (int64_t)n0 * A.s0;
   // One iteration; `rot` is the rotation after this iteration's pushes.
   auto body = [&](int z0, auto rotc) {
     constexpr int rot = decltype(rotc)::value;
     __builtin_amdgcn_sched_barrier(0);   // keep unrolled copies from overlapping (register pressure)
     float cin[RY], pin[RY], bin[T][RY];
+    float uin[ADJ ? T : 1][ADJ ? RY : 1], gin[ADJ ? T : 1][ADJ ? RY : 1];
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
       cin[i] = pc[i];
       pin[i] = pp[i];
 #pragma unroll
       for (int k = 0; k < T; ++k) bin[k][i] = pb[k][i];
+    }
+    if constexpr (ADJ) {
+      // stage 1 starts from grad; stage k > 1 from the oldest entry of its
+      // FIFO, whose entries then age by one
+#pragma unroll
+      for (int k = 1; k <= T; ++k) {   // this iteration's history planes, used after the updates
+        const rsrc_t rh = hist_rsrc(k);
+        const uint32_t sw = sg.off(z0 - k * R, za, zb);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) uin[k - 1][i] = bload(rh, ocol[i], sw);
+      }
+      const uint32_t sw = sg.off(z0 - R, za, zb);
+#pragma unroll
+      for (int i = 0; i < RY; ++i) gin[0][i] = bload(rg, ocol[i], sw);
+#pragma unroll
+      for (int i = 0; i < RY; ++i) {
+#pragma unroll
+        for (int k = 1; k < T; ++k) {
+          gin[k][i] = gq[k - 1][0][i];
+#pragma unroll
+          for (int j = 0; j + 1 < RQ; ++j) gq[k - 1][j][i] = gq[k - 1][j + 1][i];
+        }
+      }
     }
     {  // next iteration's loads first
       const int zn = z0 + 1;
@@ -681,9 +759,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
         const bool fz = EV && zk >= A.inj_zlo && zk < A.inj_zhi;
         const bool sz = EV && zown && zk >= A.smp_zlo && zk < A.smp_zhi;
         const uint32_t so = sg.off(zk, za, zb);   // stores: owned planes only
-        constexpr bool HIST = (MODE == MODE_HIST || MODE == MODE_ADJ);
-        const rsrc_t rh = HIST ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
-        const rsrc_t rg = (MODE == MODE_ADJ) ? sg.rsrc(A.grad) : ra;
+        const rsrc_t rh = (MODE == MODE_HIST) ? sg.rsrc(A.hist + (int64_t)(step + 1 - A.hist_base) * N) : ra;
         float v[RY], st[RY], upv[RY], fr[RY];
         const int ybase = gy0 + (HY ? wrow0 : 0), xbase = gx0 + (HY ? wx * 64 : wv * RY * 64);
         if (EV && fz) forcing_rows<RY, HY>(A, zk, ybase, xbase, lane, step, fr);
@@ -732,9 +808,11 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
           const uint32_t o = outoff(i);
           if (MODE == MODE_HIST) {
             bstore(rh, o, so, v[i]);
-          } else if (MODE == MODE_ADJ) {
-            const float u = bload(rh, o, so);
-            bstore(rg, o, so, image_step(bload(rg, o, so), u, st[i], v[i], win[k - 1][i][(R + rot) % W], upv[i]));
+          } else if constexpr (ADJ) {
+            const float g = image_step(gin[k - 1][i], uin[k - 1][i], st[i], v[i], win[k - 1][i][(R + rot) % W],
+                                       upv[i]);
+            if (k == T) bstore(rg, o, so, g);
+            else gq[(k >= 1 && k < T) ? k - 1 : 0][RQ - 1][i] = g;
           }
           if (k == T) {
             bstore(ra, o, so, v[i]);

@@ -165,6 +165,8 @@ def lib():
             "wave_batch": (i32, [P, i32, i32, P, P, P, P, P, P, P, P, i32, P, P]),
             "wave_autotune": (i32, [P, i32, i32, i32, P, sz, P]),
             "wave_autotune_guided": (i32, [P, i32, i32, i32, i32, P, sz, P, P]),
+            "wave_autotune_points": (i32, [P, i32, i32, i32, i32, i32, P, i32, P, P, sz, P, P]),
+            "wave_autotune_scratch_bytes": (sz, [P, i32, i32, i32]),
             "wave_tiled_max_depth": (i32, [i32, i32, i32, i32]),
             "wave_tile_extent": (i32, [i32, i32, P, P]),
             "wave_ai_naive": (dbl, [dbl, i32]),
@@ -313,6 +315,25 @@ def wave_autotune_guided(ctx, trial_steps, repeats, max_T, keep, scratch):
     best = ctypes.c_double()
     n = ctypes.c_int32()
     st = lib().wave_autotune_guided(ctx, trial_steps, repeats, max_T, keep, ctypes.c_void_p(scratch.data_ptr()),
+                                    scratch.numel() * scratch.element_size(), ctypes.byref(best), ctypes.byref(n))
+    _check(st, ctx)
+    return best.value, n.value
+
+
+def wave_autotune_scratch_bytes(ctx, trial_steps, nsrc=0, nrec=0) -> int:
+    return int(lib().wave_autotune_scratch_bytes(ctx, trial_steps, nsrc, nrec))
+
+
+def wave_autotune_points(ctx, trial_steps, repeats, max_T, keep, src_xyz, rec_xyz, scratch, ndim=3):
+    """The autotuner whose trials carry the operator's sources and
+    receivers (keep = 0: exhaustive, else estimator-guided): returns
+    (seconds per step of the schedule kept, number of candidates timed)."""
+    src = _coords(src_xyz, ndim)
+    rec = _coords(rec_xyz, ndim)
+    best = ctypes.c_double()
+    n = ctypes.c_int32()
+    st = lib().wave_autotune_points(ctx, trial_steps, repeats, max_T, keep, src.shape[0], _hptr(src), rec.shape[0],
+                                    _hptr(rec), ctypes.c_void_p(scratch.data_ptr()),
                                     scratch.numel() * scratch.element_size(), ctypes.byref(best), ctypes.byref(n))
     _check(st, ctx)
     return best.value, n.value
@@ -481,6 +502,17 @@ class WaveOp:
 
     def schedule(self) -> Schedule:
         return wave_get_schedule(self.ctx, self.ndim)
+
+    def autotune(self, trial_steps=40, repeats=2, max_T=0, src_xyz=None, rec_xyz=None, keep=0) -> float:
+        """Time the schedules with trial forwards that carry these sources
+        and receivers (wave_autotune_points; keep = 0 exhaustive, else the
+        estimator-guided tuner) and keep the fastest; returns its seconds
+        per step."""
+        nsrc = 0 if src_xyz is None else len(src_xyz)
+        nrec = 0 if rec_xyz is None else len(rec_xyz)
+        sc = self.scratch(wave_autotune_scratch_bytes(self.ctx, trial_steps, nsrc, nrec))
+        best, _ = wave_autotune_points(self.ctx, trial_steps, repeats, max_T, keep, src_xyz, rec_xyz, sc, self.ndim)
+        return best
 
     def forward(self, nt, src_xyz=None, wavelet=None, rec_xyz=None, u_init=None, want_final=False,
                 ckpt_every=0, adjoint_scratch=False):

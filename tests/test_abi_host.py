@@ -68,6 +68,12 @@ def test_flop_and_byte_counts(W):
     assert W.wave_bytes_per_point(1, 0) == 16.0
     assert W.wave_bytes_per_point(4, 0) == 5.0
     assert W.wave_bytes_per_point(2, 1) == 14.0
+    # adjoint with imaging: the history read at every step, the gradient read
+    # and written once per window: (7 + T) 4 / T for T >= 2, 28 untiled
+    assert W.wave_bytes_per_point(-1, 2) == 28.0
+    assert W.wave_bytes_per_point(1, 2) == 28.0
+    for T in (2, 3, 4, 8):
+        assert W.wave_bytes_per_point(T, 2) == pytest.approx((7 + T) * 4.0 / T, rel=1e-12)
     # explicit diffusion: centre, per axis and radius one add + one FMA, the final add;
     # one level read and one written per launch
     assert W.diff_flops_per_point(3, 8) == 2 + 3 * 3 * 4
@@ -184,3 +190,14 @@ def test_descriptor_tile_and_slab_validation(W):
     neg = W.make_desc((64, 64, 64), 10.0, 1e-3, 8, time_tile=2, slab=0)
     neg.slab = -3
     assert W.wave_state_bytes(neg) == 0
+
+
+def test_null_context_entry_points(W):
+    """Entry points refuse a null context before any device call: the
+    autotuners return WAVE_EINVAL, the sizing calls 0."""
+    L = W.lib()
+    assert L.wave_autotune_scratch_bytes(None, 10, 0, 0) == 0
+    assert L.wave_scratch_bytes(None, 10, 0, 0, 0, 0) == 0
+    assert L.wave_autotune(None, 10, 1, 0, None, 0, None) == -1
+    assert L.wave_autotune_guided(None, 10, 1, 0, 4, None, 0, None, None) == -1
+    assert L.wave_autotune_points(None, 10, 1, 0, 0, 0, None, 0, None, None, 0, None, None) == -1
