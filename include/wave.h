@@ -83,7 +83,8 @@ typedef struct wave_desc {
                             (b1 rows along axis 1, b2 columns along the unit-stride axis)
                             loaded by one workgroup, of which the inner (b1 - 2 skew T) x
                             (b2 - 2 skew T) are written (Devito chapter, "Parameterisation":
-                            tile sizes as run-time parameters).  {0, 0} = auto.  Must be an
+                            tile sizes as run-time parameters).  {0, 0} = auto: the first
+                            entry of the table below that builds depth T at this order.  Must be an
                             entry of the table of built tiles (wave_tile_extent): 3D 64x64,
                             32x64, 32x128, 16x128; 2D 1x1024.  Others: WAVE_EUNSUPPORTED */
   int32_t slab;          /* > 0 (with T >= 1): the skewed schedule of the implementation

@@ -790,7 +790,7 @@ BlockShape block_shape(int kind, int dim, int shape) {
   if (shape == 2) return {8, 4, 32, 64};
   if (shape == 3) return {16, 4, 32, 128};
   if (shape == 4) return {8, 4, 16, 128};
-  return {8, 8, 64, 64};
+  return {16, 4, 64, 64};   // 16 waves x 4 rows (1024 threads)
 }
 
 int tiled_tmax(int R, int dim, int shape) {
@@ -876,9 +876,15 @@ static wave_status apply_schedule(wave_ctx* c, int T, int skew, int shape, int s
   if (slab > 0 && T < 1) return fail(c, WAVE_EINVAL, "the skewed schedule needs a depth T >= 1");
   if (c->eq == 2 && T >= 1 && slab == 0)
     return fail(c, WAVE_EUNSUPPORTED, "the two-level step runs untiled or skewed (slab > 0) only");
+  // tile {0, 0} (shape 0): the first entry of the table that builds depth T
+  // at this order (3D)
+  int auto_shape = 1;
+  if (c->dim == 3 && shape == 0 && T >= 1 && slab == 0)
+    for (int i = kNumShapes3D; i >= 1; --i)
+      if (tiled_tmax(c->R, 3, i) >= T) auto_shape = i;
   c->T = T;
   c->skew = skew ? skew : c->R;
-  c->shape = (c->dim == 3) ? (shape ? shape : 1) : 0;
+  c->shape = (c->dim == 3) ? (shape ? shape : auto_shape) : 0;
   c->slab = slab;
   c->zchunks = zchunks;
   if (T >= 1 && slab == 0) {
@@ -1056,8 +1062,8 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
   if (T0 == -2) {
     // Default schedule from measurements on MI355X (592^3, layered model,
     // about one workgroup per CU of axis-0 segments): depth 3 on 64 x 64
-    // tiles at radius 1 in 3D (1.38x the untiled sweep), depth 2 on 32 x 128
-    // tiles at radius 2 (1.28x); from radius 3 on no time-tiled schedule
+    // tiles at radius 1 in 3D (1.51x the untiled sweep), depth 2 on 32 x 128
+    // tiles at radius 2 (1.30x); from radius 3 on no time-tiled schedule
     // beats the untiled sweep, which is the default.  wave_autotune refines
     // by timing on the actual problem.
     // 2D (16384^2, 100 steps): depth 4 up to radius 2 (2.7x, 2.3x), depth

@@ -63,10 +63,14 @@ constexpr int kBatchTmax = 2;
 // Depth limits per (radius, dim, shape), shared by host planning and the
 // instantiation units.  Bounded by the register file: every fused level keeps
 // a (2R+1)-plane window per column.
-constexpr int kTmax3D_S1[9] = {0, 4, 4, 3, 2, 2, 2, 1, 1};
+// 64 x 64 and 32 x 128: 16 waves of 4 rows (1024 threads) leave 128 registers
+// per thread, half of what the 512-thread tiles may use, so the windows of
+// fewer levels fit (deeper builds spill; radius 1 at T = 3 spills two words).
+// The 64 x 64 tile measured faster this way than as 8 waves of 8 rows (at
+// radius 1, T = 3: 431.6 against 401.3 Gpts/s on 592^3): twice the waves per
+// SIMD hide the latency that bounds it.
+constexpr int kTmax3D_S1[9] = {0, 3, 2, 1, 1, 1, 1, 1, 1};
 constexpr int kTmax3D_S2[9] = {0, 6, 6, 4, 3, 2, 2, 2, 1};
-// 32 x 128: 1024 threads leave 128 registers per thread (half of the
-// 512-thread tiles), so the windows of fewer levels fit (deeper builds spill).
 constexpr int kTmax3D_S3[9] = {0, 2, 2, 1, 1, 1, 1, 1, 1};
 // 16 x 128: bounded by the core, 16 - 2 r T >= 1 rows.
 constexpr int kTmax3D_S4[9] = {0, 6, 3, 2, 1, 1, 1, 1, 0};

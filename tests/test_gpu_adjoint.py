@@ -79,7 +79,7 @@ def test_gradient_matches_oracle(prob):
     assert_field(gq, prob["ref"]["grad_q"], TOL_GRAD, "grad_q")
 
 
-@pytest.mark.parametrize("T,shape", [(1, 1), (2, 1), (1, 2), (2, 2), (3, 2)])
+@pytest.mark.parametrize("T,shape", [(1, 1), (1, 2), (2, 2), (3, 2), (1, 3), (1, 4)])
 def test_tiled_adjoint_bitwise_equals_untiled(prob, T, shape):
     op = _op(prob, prob["m0"], time_tile=-1)
     gm_u, gq_u = _grad(op, prob, K=13)

@@ -78,7 +78,7 @@ def test_diffusion_schedules_bitwise(so, shape):
         op.set_schedule(T, 0, tshape, zc)
         assert torch.equal(op.forward(w.nt, u0), base), (T, tshape, zc)
     if len(shape) == 3 and so <= 8:   # a wider skew than the radius
-        op.set_schedule(2, so // 2 + 1, 1, 0)
+        op.set_schedule(2, so // 2 + 1, 2, 0)
         assert torch.equal(op.forward(w.nt, u0), base)
 
 

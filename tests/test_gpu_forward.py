@@ -167,7 +167,7 @@ def test_skew_and_segmentation_bitwise(skew_extra, zchunks):
     w = _small(8, (45, 70, 90), nbl=5, seed=7)
     op = _op(w, time_tile=-1)
     rec_u, fin_u = _run(op, w)
-    op.set_schedule(2, 4 + skew_extra, 1, zchunks)
+    op.set_schedule(2, 4 + skew_extra, 2, zchunks)
     rec_t, fin_t = _run(op, w)
     assert np.array_equal(fin_t, fin_u)
     assert np.array_equal(rec_t, rec_u)
@@ -177,7 +177,7 @@ def test_partial_windows_and_nt_edge_cases():
     w = _small(4, (30, 40, 50), nbl=2, seed=9, nt=7)
     op = _op(w, time_tile=-1)
     rec_u, fin_u = _run(op, w)
-    op.set_schedule(4, 0, 1, 0)          # windows 4 + 3
+    op.set_schedule(4, 0, 2, 0)          # windows 4 + 3
     rec_t, fin_t = _run(op, w)
     assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u)
     ref = _oracle(w)
