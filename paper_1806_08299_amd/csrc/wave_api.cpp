@@ -785,7 +785,7 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
 namespace wavett {
 
 BlockShape block_shape(int kind, int dim, int shape) {
-  if (dim == 2) return {4, 4, 1, 1024};
+  if (dim == 2) return {8, 2, 1, 1024};   // 8 waves x 2 slots of 64 columns
   if (kind == KIND_UNTILED) return {WAVE_UNTILED_NW, WAVE_UNTILED_RY, WAVE_UNTILED_NW * WAVE_UNTILED_RY, 64};
   if (shape == 2) return {8, 4, 32, 64};
   if (shape == 3) return {16, 4, 32, 128};
@@ -1066,10 +1066,12 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
     // tiles at radius 2 (1.30x); from radius 3 on no time-tiled schedule
     // beats the untiled sweep, which is the default.  wave_autotune refines
     // by timing on the actual problem.
-    // 2D (16384^2, 100 steps): depth 4 up to radius 2 (2.7x, 2.3x), depth
-    // 2 up to radius 4 (1.5x), untiled beyond.
+    // 2D (16384^2, 100 steps): depth 6 at radius 1 (2.8x), 4 at radius 2
+    // (2.3x), 3 at radius 4 (1.7x; radius 3 takes the same depth), untiled
+    // beyond.
     int best = -1;
-    const int Td = c->dim == 3 ? (c->R <= 1 ? 3 : (c->R == 2 ? 2 : 0)) : (c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0));
+    const int Td = c->dim == 3 ? (c->R <= 1 ? 3 : (c->R == 2 ? 2 : 0))
+                               : (c->R <= 1 ? 6 : (c->R == 2 ? 4 : (c->R <= 4 ? 3 : 0)));
     if (Td > 0) {
       const int oshape = c->shape;
       if (c->dim == 3 && shape0 == 0) c->shape = c->R <= 1 ? 1 : 3;
@@ -2042,8 +2044,9 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
   // Default from measurements on MI355X (32 steps): 3D (500^3) depth 4 on
   // 32 x 64 tiles at radius 1 (3.1x the untiled sweep), depth 2 at radius 2
   // (2.0x), the depth-1 tiled sweep on 32 x 64 tiles up to radius 4 (1.1x),
-  // untiled beyond; 2D (16384^2) depth 4 up to radius 2 (3.3x, 2.7x),
-  // depth 2 up to radius 4 (1.7x), untiled beyond.
+  // untiled beyond; 2D (16384^2, measured with the earlier 4-wave layout of
+  // the 2D tile) depth 4 up to radius 2 (3.3x, 2.7x), depth 2 up to radius 4
+  // (1.7x), untiled beyond.
   int Td = 0;
   if (c->dim == 3) Td = c->R == 1 ? 4 : (c->R == 2 ? 2 : (c->R <= 4 ? 1 : 0));
   else Td = c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0);

@@ -74,6 +74,10 @@ constexpr int kTmax3D_S2[9] = {0, 6, 6, 4, 3, 2, 2, 2, 1};
 constexpr int kTmax3D_S3[9] = {0, 2, 2, 1, 1, 1, 1, 1, 1};
 // 16 x 128: bounded by the core, 16 - 2 r T >= 1 rows.
 constexpr int kTmax3D_S4[9] = {0, 6, 3, 2, 1, 1, 1, 1, 0};
-constexpr int kTmax2D[9] = {0, 4, 4, 4, 4, 2, 2, 2, 2};
+// 2D 1 x 1024: 8 waves of 2 slots (64 columns apart); measured against 4 waves
+// of 4 slots (16384^2, 100 steps): order 2 801 against 783 Gpts/s (T = 6
+// against 4), order 8 481 against 433 (T = 3), order 4 level.  Beyond these
+// depths the windows of the fused levels leave too few waves per SIMD.
+constexpr int kTmax2D[9] = {0, 8, 8, 6, 4, 2, 2, 2, 2};
 
 }  // namespace wavett

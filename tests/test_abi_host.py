@@ -175,7 +175,7 @@ def test_tile_table_and_depth_limits(W):
         assert W.wave_tiled_max_depth(so, 3, tile=(0, 0)) == 0
     assert W.wave_tiled_max_depth(8, 3, tile=(32, 64)) == 3
     assert W.wave_tiled_max_depth(16, 3, tile=(16, 128)) == 0
-    assert W.wave_tiled_max_depth(4, 2, tile=(1, 1024)) == 4
+    assert W.wave_tiled_max_depth(4, 2, tile=(1, 1024)) == 8
     assert W.block_extent(3, 3) == (32, 128)
 
 

@@ -287,12 +287,13 @@ def test_empty_point_sets_and_degenerate_grids(shape):
 
 
 @pytest.mark.parametrize("so,shape,expect", [(2, (40, 70, 80), 3), (4, (40, 70, 80), 2), (6, (40, 70, 80), -1),
-                                               (8, (40, 70, 80), -1), (2, (50, 300), 4), (8, (50, 300), 2),
-                                               (16, (50, 300), -1)])
+                                               (8, (40, 70, 80), -1), (2, (50, 300), 6), (4, (50, 300), 4),
+                                               (6, (50, 300), 3), (8, (50, 300), 3), (16, (50, 300), -1)])
 def test_default_schedule(so, shape, expect):
     """time_tile = 0: in 3D depth 3 on 64x64 tiles at radius 1 and depth 2 on
-    32x128 tiles at radius 2; in 2D depth 4 up to radius 2 and 2 up to radius
-    4; untiled otherwise; the result is bitwise that of the untiled sweep."""
+    32x128 tiles at radius 2; in 2D depth 6 at radius 1, 4 at radius 2, 3 up
+    to radius 4; untiled otherwise; the result is bitwise that of the untiled
+    sweep."""
     w = _small(so, shape, nbl=3, seed=31, nt=10)
     op = _op(w, time_tile=0)
     T, skew, tshape, _ = op.schedule()[:4]
