@@ -368,10 +368,11 @@ typedef struct diff_desc {
   double dt;             /* time step */
   double alpha;          /* diffusivity a (> 0); units spacing^2 / time */
   int32_t time_tile;     /* -1: untiled sweep; T >= 1: fused steps per launch; 0: default
-                            (3D: T = 4 at radius 1, T = 2 at radius 2, T = 1 up to
-                            radius 4, on 32x64 tiles; 2D: T = 4 up to radius 2, T = 2
-                            up to radius 4; untiled otherwise -- the measured best on
-                            MI355X) */
+                            (3D: T = 4 at radius 1, T = 2 at radius 2, on 32x64 tiles;
+                            at radii 3 and 4 the skewed schedule, T = 8 on slabs of 64
+                            planes in 2 segments (grids deeper than 64 planes); 2D:
+                            T = 4 up to radius 2, T = 2 up to radius 4; untiled
+                            otherwise -- measured on MI355X) */
   int32_t skew;          /* 0 = r; must be >= r */
   int32_t tile[2];       /* as in wave_desc */
   int32_t slab;          /* as in wave_desc */

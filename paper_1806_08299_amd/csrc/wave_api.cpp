@@ -787,7 +787,7 @@ namespace wavett {
 BlockShape block_shape(int kind, int dim, int shape) {
   if (dim == 2) return {8, 2, 1, 1024};   // 8 waves x 2 slots of 64 columns
   if (kind == KIND_UNTILED) return {WAVE_UNTILED_NW, WAVE_UNTILED_RY, WAVE_UNTILED_NW * WAVE_UNTILED_RY, 64};
-  if (shape == 2) return {8, 4, 32, 64};
+  if (shape == 2) return {16, 2, 32, 64};   // 16 waves x 2 rows (1024 threads)
   if (shape == 3) return {16, 4, 32, 128};
   if (shape == 4) return {8, 4, 16, 128};
   return {16, 4, 64, 64};   // 16 waves x 4 rows (1024 threads)
@@ -2042,13 +2042,15 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
     return s;
   }
   // Default from measurements on MI355X (32 steps): 3D (500^3) depth 4 on
-  // 32 x 64 tiles at radius 1 (3.1x the untiled sweep), depth 2 at radius 2
-  // (2.0x), the depth-1 tiled sweep on 32 x 64 tiles up to radius 4 (1.1x),
-  // untiled beyond; 2D (16384^2, measured with the earlier 4-wave layout of
-  // the 2D tile) depth 4 up to radius 2 (3.3x, 2.7x), depth 2 up to radius 4
-  // (1.7x), untiled beyond.
+  // 32 x 64 tiles at radius 1 (3.2x the untiled sweep), depth 2 at radius 2
+  // (1.9x); at radii 3 and 4 the skewed schedule, depth 8 on 64-plane slabs
+  // in 2 segments (500^3: 1.20x and 1.10x; 600^3: 1.05x and 0.98x -- no
+  // register-tiled depth held up on both grids); untiled beyond.  2D
+  // (16384^2, measured with the earlier 4-wave layout of the 2D tile) depth
+  // 4 up to radius 2 (3.3x, 2.7x), depth 2 up to radius 4 (1.7x), untiled
+  // beyond.
   int Td = 0;
-  if (c->dim == 3) Td = c->R == 1 ? 4 : (c->R == 2 ? 2 : (c->R <= 4 ? 1 : 0));
+  if (c->dim == 3) Td = c->R == 1 ? 4 : (c->R == 2 ? 2 : 0);
   else Td = c->R <= 2 ? 4 : (c->R <= 4 ? 2 : 0);
   if (d->time_tile == 0 && Td > 0 && c->eq == 1) {
     const int oshape = c->shape;
@@ -2056,6 +2058,10 @@ wave_status diff_init(const diff_desc* d, void* state, size_t state_bytes, void*
     Plan pl;
     if (make_plan(c, KIND_TILED, Td, pl) == WAVE_OK) c->T = Td;
     else c->shape = oshape;
+  } else if (d->time_tile == 0 && c->eq == 1 && c->dim == 3 && (c->R == 3 || c->R == 4) && c->n0 > 64) {
+    c->T = 8;
+    c->slab = 64;
+    c->zchunks = d->zchunks ? d->zchunks : 2;
   }
   c->err.clear();
   *out = c;

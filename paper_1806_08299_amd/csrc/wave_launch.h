@@ -70,6 +70,13 @@ constexpr int kBatchTmax = 2;
 // radius 1, T = 3: 431.6 against 401.3 Gpts/s on 592^3): twice the waves per
 // SIMD hide the latency that bounds it.
 constexpr int kTmax3D_S1[9] = {0, 3, 2, 1, 1, 1, 1, 1, 1};
+// 32 x 64: 16 waves of 2 rows (1024 threads), measured against 8 waves of 4
+// rows (592^3 wave sweep at order 2: T = 3 422.7 against 390.5 Gpts/s; the
+// Laplace operator, 500^3: order 2 T = 4 1434.8 against 1372.0, order 4 T = 3
+// 686.4 against 578.5; order 4 T = 2 of the wave sweep 304.0 against 327.7,
+// where 32 x 128 is faster than either).  Spill-free up to depth 6, 4, 3, 2,
+// 2, 2, 1, 1 at radii 1..8; the deeper entries below spill and stay built for
+// the depth sweeps.
 constexpr int kTmax3D_S2[9] = {0, 6, 6, 4, 3, 2, 2, 2, 1};
 constexpr int kTmax3D_S3[9] = {0, 2, 2, 1, 1, 1, 1, 1, 1};
 // 16 x 128: bounded by the core, 16 - 2 r T >= 1 rows.

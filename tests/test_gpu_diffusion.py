@@ -111,20 +111,25 @@ def test_diffusion_edge_cases():
             assert torch.equal(o.forward(t.nt, torch.from_numpy(t.u0).cuda()), got)
 
 
-@pytest.mark.parametrize("so,shape,expect", [(2, (40, 50, 130), 4), (4, (40, 50, 130), 2), (8, (40, 50, 130), 1),
+@pytest.mark.parametrize("so,shape,expect", [(2, (40, 50, 130), 4), (4, (40, 50, 130), 2), (8, (40, 50, 130), -1),
+                                            (6, (90, 40, 70), 8), (8, (90, 40, 70), 8), (16, (90, 40, 70), -1),
                                             (16, (40, 50, 130), -1), (2, (60, 2100), 4), (8, (60, 2100), 2),
                                             (16, (60, 2100), -1)])
 def test_diffusion_default_schedule(so, shape, expect):
-    """time_tile = 0: 3D depth 4 (radius 1), 2 (radius 2) or 1 (up to radius
-    4) on 32x64 tiles;
-    2D depth 4 up to radius 2, 2 up to radius 4; untiled otherwise; bitwise
-    the untiled result."""
+    """time_tile = 0: 3D depth 4 (radius 1) or 2 (radius 2) on 32x64 tiles,
+    the skewed schedule at depth 8 on 64-plane slabs at radii 3 and 4 (grids
+    deeper than 64 planes); 2D depth 4 up to radius 2, 2 up to radius 4;
+    untiled otherwise; bitwise the untiled result."""
     w = wi.laplace(shape=shape, so=so, nt=9, seed=2)
     op = _op(w, time_tile=0)
-    T, skew, tshape, _ = op.schedule()[:4]
+    sch = op.schedule()
+    T, skew, tshape, _ = sch[:4]
     assert T == expect and skew == so // 2
     if T > 0 and len(shape) == 3:
-        assert tshape == 2
+        if so <= 4:
+            assert tshape == 2 and sch.slab == 0
+        else:
+            assert sch.slab == 64 and sch.zchunks == 2
     u0 = torch.from_numpy(w.u0).cuda()
     got = op.forward(w.nt, u0)
     op.set_schedule(-1, 0, 0, 0)
