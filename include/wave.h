@@ -253,7 +253,10 @@ wave_status wave_batch(wave_ctx* const* ctxs, int32_t nshots, int32_t nt,
  * register-tiled schedule, or the slab thickness and depth of the best skewed
  * one (the paper's skew experiment, "Effect of the skewing factor").  Keeps
  * the fastest; a time-tiled schedule replaces the untiled sweep only when
- * faster by more than 1 % (the trials' run-to-run spread).  Synchronises;
+ * faster by more than 1 % (the trials' run-to-run spread), and among untiled
+ * segment counts within 1 % of the fastest the largest is kept (the forward
+ * trials rarely separate them, while the gradient's history and adjoint
+ * sweeps of the same schedule run faster with more workgroups).  Synchronises;
  * needs scratch for `trial_steps` forward steps without sources
  * (wave_scratch_bytes(ctx, trial_steps, 0, 0, 0, 0)).  On a diffusion
  * context (diff_init) the trials are diff_forward calls from a zero field

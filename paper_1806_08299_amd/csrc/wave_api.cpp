@@ -1728,13 +1728,19 @@ wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, 
   std::stable_sort(timed.begin(), timed.end(), better);
   double best_t = timed.empty() ? 1e300 : timed[0].first;
   Cand bc = timed.empty() ? Cand{oT, os, osh, osl, oz} : timed[0].second;
-  // the fastest untiled timing, for the final choice below
+  // the fastest untiled timing, for the final choice below, and every
+  // untiled timing (for the segment-count preference)
   double best_untiled = 1e300;
   Cand bu = cands[0];
+  std::vector<std::pair<double, Cand>> untiled_t;
   for (const auto& tk : timed)
-    if (tk.second.T < 0 && tk.first < best_untiled) { best_untiled = tk.first; bu = tk.second; }
+    if (tk.second.T < 0) {
+      untiled_t.push_back(tk);
+      if (tk.first < best_untiled) { best_untiled = tk.first; bu = tk.second; }
+    }
   auto consider = [&](const Cand& k) {
     const double t = timed_one(k);
+    if (k.T < 0) untiled_t.push_back({t, k});
     if (k.T < 0 && t < best_untiled) { best_untiled = t; bu = k; }
     if (t < best_t) {
       best_t = t;
@@ -1787,6 +1793,22 @@ wave_status autotune_impl(wave_ctx* c, int trial_steps, int repeats, int max_T, 
       Cand k = b1;
       k.T = T;
       consider(k);
+    }
+  }
+  // Among untiled segment counts within the trials' spread (1 %) of the
+  // fastest, the largest: the forward trials often cannot tell them apart,
+  // while the gradient's history and adjoint sweeps of the same schedule run
+  // faster with more workgroups (336^3, order 8: 231 against 242 us per
+  // adjoint launch with 32 segments against 12, the forward level).
+  if (best_untiled < 1e300) {
+    const BlockShape ubs = block_shape(KIND_UNTILED, c->dim, 0);
+    const int64_t ubase = (int64_t)((c->n2 + ubs.ex - 1) / ubs.ex) * ((c->n1 + ubs.ey - 1) / ubs.ey);
+    auto segs = [&](const Cand& k) { return k.zc > 0 ? k.zc : auto_zchunks(c, ubase, KIND_UNTILED, 1, c->n0); };
+    for (const auto& tk : untiled_t)
+      if (tk.first <= 1.01 * best_untiled && segs(tk.second) > segs(bu)) bu = tk.second;
+    if (bc.T < 0) {
+      best_t = std::min(best_t, best_untiled);
+      bc = bu;
     }
   }
   // A time-tiled schedule replaces the untiled sweep only when it is faster
