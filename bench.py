@@ -302,7 +302,10 @@ def gradient_bench(args, dev, stream):
     op = WaveOp(init.shape, init.spacing, init.dt, init.so, torch.from_numpy(init.m).to(dev), nbl=init.nbl,
                 sigma_max=init.sigma_max, time_tile=-1)
     wv = torch.from_numpy(init.wavelet).to(dev)
-    autotune(op, init)
+    if args.T != 0:     # a schedule pinned on the command line (profiling runs) instead of the autotuner's
+        op.set_schedule(args.T, 0, args.shape if args.slab == 0 else 0, args.zchunks, slab=args.slab)
+    else:
+        autotune(op, init)
     tuned = op.schedule()
     out = {"workload": "%s, model %s, nt=%d, checkpoints every %d"
                        % (init.name, "x".join(map(str, init.shape)), init.nt, K), "unit": "Gpts/s"}
