@@ -669,6 +669,68 @@ def depth_sweep(op, w, wav, stream, nt=40):
     return rows
 
 
+def skew_sweep(dev, stream, quick=False, nt=40):
+    """The paper's skewing-factor experiment (Evaluation, Effect of the
+    skewing factor): the minimum legal skew r against larger ones (r, 3r/2,
+    2r) for the best register tiles and the skewed schedule of the layered
+    workload at orders 4 and 8 (nt-step slices), and for the Laplace
+    operator at order 8 (500^3, 32 steps: the grid of the paper's note on
+    skews 4 and 8).  A skew that leaves a tile no core reads 'no core'."""
+    import torch
+    import waveinputs as wi
+    from paper_1806_08299_amd import DiffOp, WaveError, WaveOp
+    from paper_1806_08299_amd.wave import Schedule, tile_table
+    tab = tile_table(3)
+    n = 128 if quick else 512
+    rows = []
+    for so, cfgs in ((4, [(2, (32, 128), 0), (8, (0, 0), 64)]),
+                     (8, [(1, (32, 128), 0), (2, (32, 64), 0), (8, (0, 0), 64)])):
+        r = so // 2
+        skews = sorted({r, (3 * r + 1) // 2, 2 * r})
+        w = wi.layered_512(nt=nt, n=n, so=so)
+        op = WaveOp(w.shape, w.spacing, w.dt, w.so, torch.from_numpy(w.m).to(dev), nbl=w.nbl,
+                    sigma_max=w.sigma_max, time_tile=-1)
+        wav = torch.from_numpy(w.wavelet).to(dev)
+        for T, tile, slab in cfgs:
+            shape = tab.index(tile) + 1 if slab == 0 else 0
+            by = {}
+            for sk in skews:
+                v = _rate(op, nt, w, wav, stream, 2, Schedule(T, sk, shape, 2 if slab else 0, tile, slab))
+                by[str(sk)] = round(v, 1) if v > 0 else "no core"
+            kind = "skewed, %d-plane slabs" % slab if slab else "register-tiled %dx%d" % tile
+            rows.append({"workload": w.name, "space_order": so, "T": T, "kind": kind, "unit": "Gpts/s",
+                         "by_skew": by})
+            log("skew sweep so%d T=%d %s: %s" % (so, T, kind, by))
+        del op
+        torch.cuda.empty_cache()
+    w = wi.laplace(n=128 if quick else 500, so=8, nt=32)
+    d = DiffOp(w.shape, w.spacing, w.dt, w.alpha, w.so)
+    u0 = torch.from_numpy(w.u0).to(dev)
+    for T, tile, slab, zc in ((8, (0, 0), 64, 2), (1, (32, 128), 0, 4)):
+        by = {}
+        for sk in (4, 6, 8):
+            try:
+                d.set_schedule(T, sk, tab.index(tile) + 1 if slab == 0 else 0, zc, slab=slab)
+            except WaveError:
+                by[str(sk)] = "no core"
+                continue
+            d.forward(w.nt, u0)
+            best = 1e30
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                d.forward(w.nt, u0)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            by[str(sk)] = round(w.npts * w.nt / best / 1e9, 1)
+        kind = "skewed, %d-plane slabs" % slab if slab else "register-tiled %dx%d" % tile
+        rows.append({"workload": w.name, "space_order": 8, "T": T, "kind": kind, "unit": "Gpts/s", "by_skew": by})
+        log("skew sweep laplace so8 T=%d %s: %s" % (T, kind, by))
+    del d
+    torch.cuda.empty_cache()
+    return rows
+
+
 def c3_bench(dev, stream, quick=False):
     """768^3 (+40 = 848^3), smooth random model, space orders 12 and 16, 500
     steps: the autotuned schedule, the untiled sweep and the best time-tiled
@@ -921,6 +983,7 @@ def main():
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-operator (diffusion) section")
     ap.add_argument("--no-c1", action="store_true", help="skip the 64^3 point-source section")
     ap.add_argument("--no-depths", action="store_true", help="skip the depth sweep of the headline workload")
+    ap.add_argument("--no-skew", action="store_true", help="skip the skewing-factor sweep")
     ap.add_argument("--no-smooth", action="store_true", help="skip the 768^3 smooth-model section")
     ap.add_argument("--no-2d", action="store_true", help="skip the 2D section")
     ap.add_argument("--no-ab2", action="store_true", help="skip the two-level (Adams-Bashforth) section")
@@ -1078,6 +1141,7 @@ def main():
     del op, m, wav
     torch.cuda.empty_cache()
 
+    skews = None if args.no_skew else skew_sweep(dev, stream, quick=args.quick)
     c1 = None if args.no_c1 else c1_bench(dev, stream)
     c3 = None if args.no_smooth else c3_bench(dev, stream, quick=args.quick)
     w2d = None if args.no_2d else wave2d_bench(dev, stream, quick=args.quick)
@@ -1110,6 +1174,7 @@ def main():
         "batch": batch,
         "tiling_by_order": orders,
         "depth_sweep": depths,
+        "skew_sweep": skews,
         "point_source_64": c1,
         "smooth_768": c3,
         "wave2d": w2d,
