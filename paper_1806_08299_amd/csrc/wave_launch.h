@@ -9,11 +9,12 @@ enum : int { KIND_UNTILED = 0, KIND_TILED = 1 };
 
 // Thread-block shapes.  Untiled: core TY x TX.  Tiled: extended tile EY x EX.
 //   3D untiled        4 waves x 4 rows       -> 16 x 64 core (256 threads)
-//   3D tiled, shape 1 8 waves x 8 rows       -> 64 x 64 extended tile (512 threads)
-//   3D tiled, shape 2 8 waves x 4 rows       -> 32 x 64 extended tile (512 threads)
+//   3D tiled, shape 1 16 waves x 4 rows      -> 64 x 64 extended tile (1024 threads)
+//   3D tiled, shape 2 16 waves x 2 rows      -> 32 x 64 extended tile (1024 threads)
 //   3D tiled, shape 3 8 x 2 waves x 4 rows   -> 32 x 128 extended tile (1024 threads)
 //   3D tiled, shape 4 4 x 2 waves x 4 rows   -> 16 x 128 extended tile (512 threads)
-//   2D (both)         4 waves x 4 segments   -> 1 x 1024 (256 threads)
+//   2D untiled        4 waves x 4 segments   -> 1 x 1024 (256 threads)
+//   2D tiled          8 waves x 2 segments   -> 1 x 1024 (512 threads)
 struct BlockShape { int nw, ry, ey, ex; };
 constexpr int kNumShapes3D = 4;
 // Untiled 3D block: waves x rows per thread (core 16 x 64 by default).
