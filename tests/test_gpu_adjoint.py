@@ -219,3 +219,23 @@ def test_windowed_imaging_every_depth_bitwise(so):
                 op.set_schedule(T, 0, idx + 1, zc)
                 gm_t, gq_t = _grad(op, P, K=9)
                 assert np.array_equal(gm_t, gm_u) and np.array_equal(gq_t, gq_u), (so, tile, T, zc)
+
+
+@pytest.mark.parametrize("so", [2, 4, 8])
+def test_windowed_imaging_2d_every_depth_bitwise(so):
+    """2D register tiles (1 x 1024) at every built depth, one and several
+    axis-0 segments: gradient and source-side adjoint bitwise those of the
+    untiled sweep (the imaging sums carried across each window's stages)."""
+    from paper_1806_08299_amd.wave import wave_tiled_max_depth
+    P = _problem(so=so, shape=(70, 1100), nbl=5, nt=19, seed=50 + so, nsrc=2, nrec=9)
+    fw = oracle.forward(P["g"], P["m0"].astype(np.float64), P["nt"], P["src"], P["wav"], P["rec"])
+    P["resid"] = fw["rec"].astype(np.float32)
+    op = _op(P, P["m0"], time_tile=-1)
+    gm_u, gq_u = _grad(op, P, K=10)
+    assert np.abs(gm_u).max() > 0
+    for T in range(1, wave_tiled_max_depth(so, 2) + 1):
+        for zc in (0, 3):
+            print("2D so %d T %d zchunks %d" % (so, T, zc), flush=True)
+            op.set_schedule(T, 0, 0, zc)
+            gm_t, gq_t = _grad(op, P, K=10)
+            assert np.array_equal(gm_t, gm_u) and np.array_equal(gq_t, gq_u), (so, T, zc)

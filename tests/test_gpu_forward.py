@@ -340,3 +340,21 @@ def test_dense_receiver_lines_on_adjacent_rows(shape):
             continue
         rec_t, fin_t = _run(op, w)
         assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u), (T, shp)
+
+
+@pytest.mark.parametrize("so,T,expect", [(2, 3, (64, 64)), (2, 4, (32, 64)), (4, 2, (64, 64)), (4, 3, (32, 64)),
+                                         (8, 1, (64, 64)), (8, 2, (32, 64)), (8, 3, (32, 64))])
+def test_auto_tile_is_first_entry_holding_the_depth(so, T, expect):
+    """An explicit depth with tile {0, 0}: the first entry of the table of
+    built tiles whose depth limit at this order holds T, and the result
+    bitwise that of the untiled sweep."""
+    from paper_1806_08299_amd.wave import tile_table, wave_tiled_max_depth
+    first = next(t for t in tile_table(3) if wave_tiled_max_depth(so, 3, tile=t) >= T)
+    assert first == expect
+    w = _small(so, (40, 70, 80), nbl=3, seed=33, nt=9)
+    op = _op(w, time_tile=T)
+    assert op.schedule().T == T and op.schedule().tile == expect
+    rec_t, fin_t = _run(op, w)
+    op.set_schedule(-1, 0, 0, 0)
+    rec_u, fin_u = _run(op, w)
+    assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u)
