@@ -58,12 +58,20 @@ def test_skewed_gradient_bitwise():
     P["resid"] = np.random.default_rng(5).standard_normal((P["nt"], P["rec"].shape[0])).astype(np.float32)
     op = _aop(P, P["m0"], time_tile=-1)
     g_u, q_u = _grad(op, P, 7)
-    for T, Z, K in [(4, 10, 7), (8, 16, 40), (3, 5, 13)]:
-        print("gradient skewed T=%d slab=%d K=%d" % (T, Z, K), flush=True)
-        op.set_schedule(T, 0, 0, 0, slab=Z)
+    for T, Z, K, zc in [(4, 10, 7, 0), (8, 16, 40, 0), (3, 5, 13, 0), (6, 12, 9, 3), (2, 7, 5, 2)]:
+        print("gradient skewed T=%d slab=%d K=%d zchunks=%d" % (T, Z, K, zc), flush=True)
+        op.set_schedule(T, 0, 0, zc, slab=Z)
         g_t, q_t = _grad(op, P, K)
-        assert np.array_equal(g_t, g_u), (T, Z, K)
-        assert np.array_equal(q_t, q_u), (T, Z, K)
+        assert np.array_equal(g_t, g_u), (T, Z, K, zc)
+        assert np.array_equal(q_t, q_u), (T, Z, K, zc)
+    # the untiled sweep in several axis-0 segments (its adjoint fetches the
+    # history and the gradient two planes ahead, up to each segment's end)
+    for zc in (2, 5, 36):
+        print("gradient untiled zchunks=%d" % zc, flush=True)
+        op.set_schedule(-1, 0, 0, zc)
+        g_t, q_t = _grad(op, P, 11)
+        assert np.array_equal(g_t, g_u), zc
+        assert np.array_equal(q_t, q_u), zc
 
 
 @pytest.mark.parametrize("so", [2, 8, 16])
