@@ -71,7 +71,7 @@ typedef struct wave_desc {
   double sigma_max;      /* damping maximum in 1/s (ignored if nbl == 0) */
   int32_t time_tile;     /* T >= 1 time steps per time tile; -1 = untiled single-step
                             sweep (the reference schedule); 0 = default: 3D T = 3 on
-                            64x64 tiles at radius 1, T = 2 on 32x128 tiles at radius 2;
+                            32x128 tiles at radius 1, T = 2 on 32x128 tiles at radius 2;
                             2D T = 6 at radius 1, 4 at radius 2, 3 up to radius 4; untiled
                             otherwise (the measured best on MI355X; wave_autotune
                             refines by timing) */

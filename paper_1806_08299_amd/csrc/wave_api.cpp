@@ -1061,9 +1061,9 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
   }
   if (T0 == -2) {
     // Default schedule from measurements on MI355X (592^3, layered model,
-    // about one workgroup per CU of axis-0 segments): depth 3 on 64 x 64
-    // tiles at radius 1 in 3D (1.51x the untiled sweep), depth 2 on 32 x 128
-    // tiles at radius 2 (1.30x); from radius 3 on no time-tiled schedule
+    // about one workgroup per CU of axis-0 segments): depth 3 on 32 x 128
+    // tiles at radius 1 in 3D (1.92x the untiled sweep), depth 2 on 32 x 128
+    // tiles at radius 2 (1.45x); from radius 3 on no time-tiled schedule
     // beats the untiled sweep, which is the default.  wave_autotune refines
     // by timing on the actual problem.
     // 2D (16384^2, 100 steps): depth 6 at radius 1 (2.8x), 4 at radius 2
@@ -1074,7 +1074,7 @@ wave_status wave_init(const wave_desc* d, const float* m, void* state, size_t st
                                : (c->R <= 1 ? 6 : (c->R == 2 ? 4 : (c->R <= 4 ? 3 : 0)));
     if (Td > 0) {
       const int oshape = c->shape;
-      if (c->dim == 3 && shape0 == 0) c->shape = c->R <= 1 ? 1 : 3;
+      if (c->dim == 3 && shape0 == 0) c->shape = 3;
       Plan pl;
       if (make_plan(c, KIND_TILED, Td, pl) == WAVE_OK) best = Td;
       else c->shape = oshape;

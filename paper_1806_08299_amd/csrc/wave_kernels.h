@@ -642,7 +642,21 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
 #pragma unroll
         for (int i = 0; i < RY; ++i) gq[k][j][i] = 0.0f;
   }
-  float pc[RY], pp[RY], pb[T][RY];   // next iteration's loads
+  // b = dt^2/m: stage k + 1 needs at each iteration the value that stage k
+  // used R iterations earlier (the same plane), so b is loaded once, for
+  // stage 1, and carried to the later stages through R-entry register FIFOs
+  // (bq[k-1]: stage k's values of the last R iterations, oldest first)
+  // instead of T loads per plane.  Up to radius 2: there the FIFOs cost no
+  // more registers than the loads they replace (592^3, order 2, T = 3 on
+  // 64 x 64: 507.8 against 431.0 Gpts/s; order 4, T = 2 on 32 x 128: 419.2
+  // against 375.9; 16384^2 2D orders 2 / 4: 935.5 / 717.2 against 801.8 /
+  // 655.8).  Their (T-1) R entries per row outgrow the saving beyond that
+  // (2D order 8, T = 3: 367.6 against 481.7).
+  constexpr bool CB = !DF && T >= 2 && R <= 2;
+  constexpr int NB = CB ? 1 : T;             // b planes loaded per iteration
+  constexpr int TB = CB ? T - 1 : 1, RB = CB ? R : 1;
+  float bq[TB][RB][RY];
+  float pc[RY], pp[RY], pb[NB][RY];   // next iteration's loads
   {
     const uint32_t sc = sg.off(zs), sp = sg.off(zs - R);
 #pragma unroll
@@ -651,10 +665,20 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
       pp[i] = DF ? 0.0f : bload(rp, col[i], sp);
     }
 #pragma unroll
-    for (int k = 0; k < T; ++k) {
+    for (int k = 0; k < NB; ++k) {
       const uint32_t sb = sg.off(zs - (k + 1) * R);
 #pragma unroll
       for (int i = 0; i < RY; ++i) pb[k][i] = DF ? 0.0f : bload(rb, col[i], sb);
+    }
+    if constexpr (CB) {   // the FIFOs as if the pipeline had run before zs
+#pragma unroll
+      for (int k = 1; k < T; ++k)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          const uint32_t sb = sg.off(zs - R + j - k * R);
+#pragma unroll
+          for (int i = 0; i < RY; ++i) bq[k - 1][j][i] = bload(rb, col[i], sb);
+        }
     }
   }
   __syncthreads();
@@ -669,8 +693,20 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
     for (int i = 0; i < RY; ++i) {
       cin[i] = pc[i];
       pin[i] = pp[i];
+      if constexpr (CB) {
+        bin[0][i] = pb[0][i];
 #pragma unroll
-      for (int k = 0; k < T; ++k) bin[k][i] = pb[k][i];
+        for (int k = 1; k < T; ++k) bin[k][i] = bq[(k >= 1 && k < T) ? k - 1 : 0][0][i];
+#pragma unroll
+        for (int k = 1; k < T; ++k) {
+#pragma unroll
+          for (int j = 0; j + 1 < RB; ++j) bq[k - 1][j][i] = bq[k - 1][j + 1][i];
+          bq[k - 1][RB - 1][i] = bin[k - 1][i];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < T; ++k) bin[k][i] = pb[(k < NB) ? k : 0][i];
+      }
     }
     if constexpr (ADJ) {
       // stage 1 starts from grad; stage k > 1 from the oldest entry of its
@@ -705,7 +741,7 @@ __global__ __launch_bounds__(64 * NW) void k_tiled(typename LaunchArgs<BATCH>::t
       }
       if constexpr (!DF) {
 #pragma unroll
-        for (int k = 0; k < T; ++k) {
+        for (int k = 0; k < NB; ++k) {
           const uint32_t sb = sg.off(zn - (k + 1) * R);
 #pragma unroll
           for (int i = 0; i < RY; ++i) pb[k][i] = bload(rb, col[i], sb);

@@ -66,11 +66,12 @@ constexpr int kBatchTmax = 2;
 // a (2R+1)-plane window per column.
 // 64 x 64 and 32 x 128: 16 waves of 4 rows (1024 threads) leave 128 registers
 // per thread, half of what the 512-thread tiles may use, so the windows of
-// fewer levels fit (deeper builds spill; radius 1 at T = 3 spills two words).
+// fewer levels fit (deeper builds spill; at radius 1, with b carried from
+// stage to stage, T = 3 fits both tiles and T = 4 on 64 x 64 spills 36 bytes).
 // The 64 x 64 tile measured faster this way than as 8 waves of 8 rows (at
 // radius 1, T = 3: 431.6 against 401.3 Gpts/s on 592^3): twice the waves per
 // SIMD hide the latency that bounds it.
-constexpr int kTmax3D_S1[9] = {0, 3, 2, 1, 1, 1, 1, 1, 1};
+constexpr int kTmax3D_S1[9] = {0, 4, 2, 1, 1, 1, 1, 1, 1};
 // 32 x 64: 16 waves of 2 rows (1024 threads), measured against 8 waves of 4
 // rows (592^3 wave sweep at order 2: T = 3 422.7 against 390.5 Gpts/s; the
 // Laplace operator, 500^3: order 2 T = 4 1434.8 against 1372.0, order 4 T = 3
@@ -79,7 +80,7 @@ constexpr int kTmax3D_S1[9] = {0, 3, 2, 1, 1, 1, 1, 1, 1};
 // 2, 2, 1, 1 at radii 1..8; the deeper entries below spill and stay built for
 // the depth sweeps.
 constexpr int kTmax3D_S2[9] = {0, 6, 6, 4, 3, 2, 2, 2, 1};
-constexpr int kTmax3D_S3[9] = {0, 2, 2, 1, 1, 1, 1, 1, 1};
+constexpr int kTmax3D_S3[9] = {0, 3, 2, 1, 1, 1, 1, 1, 1};
 // 16 x 128: bounded by the core, 16 - 2 r T >= 1 rows.
 constexpr int kTmax3D_S4[9] = {0, 6, 3, 2, 1, 1, 1, 1, 0};
 // 2D 1 x 1024: 8 waves of 2 slots (64 columns apart); measured against 4 waves

@@ -290,7 +290,7 @@ def test_empty_point_sets_and_degenerate_grids(shape):
                                                (8, (40, 70, 80), -1), (2, (50, 300), 6), (4, (50, 300), 4),
                                                (6, (50, 300), 3), (8, (50, 300), 3), (16, (50, 300), -1)])
 def test_default_schedule(so, shape, expect):
-    """time_tile = 0: in 3D depth 3 on 64x64 tiles at radius 1 and depth 2 on
+    """time_tile = 0: in 3D depth 3 on 32x128 tiles at radius 1 and depth 2 on
     32x128 tiles at radius 2; in 2D depth 6 at radius 1, 4 at radius 2, 3 up
     to radius 4; untiled otherwise; the result is bitwise that of the untiled
     sweep."""
@@ -299,7 +299,7 @@ def test_default_schedule(so, shape, expect):
     T, skew, tshape, _ = op.schedule()[:4]
     assert T == expect and skew == so // 2
     if T > 0 and len(shape) == 3:
-        assert op.schedule().tile == ((64, 64) if so == 2 else (32, 128))
+        assert op.schedule().tile == (32, 128)
     rec_d, fin_d = _run(op, w)
     op.set_schedule(-1, 0, 0, 0)
     rec_u, fin_u = _run(op, w)
@@ -342,7 +342,8 @@ def test_dense_receiver_lines_on_adjacent_rows(shape):
         assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u), (T, shp)
 
 
-@pytest.mark.parametrize("so,T,expect", [(2, 3, (64, 64)), (2, 4, (32, 64)), (4, 2, (64, 64)), (4, 3, (32, 64)),
+@pytest.mark.parametrize("so,T,expect", [(2, 3, (64, 64)), (2, 4, (64, 64)), (2, 5, (32, 64)), (4, 2, (64, 64)),
+                                         (4, 3, (32, 64)),
                                          (8, 1, (64, 64)), (8, 2, (32, 64)), (8, 3, (32, 64))])
 def test_auto_tile_is_first_entry_holding_the_depth(so, T, expect):
     """An explicit depth with tile {0, 0}: the first entry of the table of
