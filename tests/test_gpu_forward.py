@@ -359,3 +359,21 @@ def test_auto_tile_is_first_entry_holding_the_depth(so, T, expect):
     op.set_schedule(-1, 0, 0, 0)
     rec_u, fin_u = _run(op, w)
     assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u)
+
+
+@pytest.mark.parametrize("so", [2, 4])
+def test_carried_b_across_segments_bitwise(so):
+    """Up to radius 2 the register tiles load b once per plane and carry it
+    from stage to stage, filling the carry from the planes below each axis-0
+    segment before the first iteration: every built tile and depth in three
+    and in seven segments, bitwise the untiled sweep (fields and traces)."""
+    w = _small(so, (70, 60, 140), nbl=4, seed=90 + so, nt=14)
+    op = _op(w, time_tile=-1)
+    rec_u, fin_u = _run(op, w)
+    for T, shp in _schedules(so // 2, 3):
+        for zc in (3, 7):
+            if not _try_schedule(op, T, shp, zchunks=zc):
+                continue
+            print("so %d T %d shape %d zchunks %d" % (so, T, shp, zc), flush=True)
+            rec_t, fin_t = _run(op, w)
+            assert np.array_equal(fin_t, fin_u) and np.array_equal(rec_t, rec_u), (so, T, shp, zc)
