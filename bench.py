@@ -305,7 +305,8 @@ def gradient_bench(args, dev, stream):
     if args.T != 0:     # a schedule pinned on the command line (profiling runs) instead of the autotuner's
         op.set_schedule(args.T, 0, args.shape if args.slab == 0 else 0, args.zchunks, slab=args.slab)
     else:
-        autotune(op, init)
+        op.autotune_gradient(40, 2, 8, init.src_xyz, init.rec_xyz, ckpt_every=20)
+        op._scratch = None
     tuned = op.schedule()
     out = {"workload": "%s, model %s, nt=%d, checkpoints every %d"
                        % (init.name, "x".join(map(str, init.shape)), init.nt, K), "unit": "Gpts/s"}
@@ -367,14 +368,14 @@ def gradient_bench(args, dev, stream):
 
 def gradient_orders(init, dev, stream, nt, K):
     """The same gradient problem (model, geometry, dt) at space orders 2 and
-    4 over nt steps: the fastest of the forward-autotuned schedule and the
-    register tiles of depth 2..4 on 32x64 and 32x128, timed on the gradient,
+    4 over nt steps: the schedule of the gradient autotuner
+    (wave_autotune_gradient) and, for reference, the forward autotuner's,
     against the untiled sweep.  The time-tiled adjoint carries each point's
     imaging sum across its window in registers, so the gradient is read and
     written once per window."""
     import torch
     from paper_1806_08299_amd import WaveOp
-    from paper_1806_08299_amd.wave import Schedule, tile_table, wave_bytes_per_point, wave_tiled_max_depth
+    from paper_1806_08299_amd.wave import wave_bytes_per_point
     wv = torch.from_numpy(np.ascontiguousarray(init.wavelet[:nt])).to(dev)
     rows = []
     for so in (2, 4):
@@ -401,23 +402,16 @@ def gradient_orders(init, dev, stream, nt, K):
             return best, gm.cpu()
 
         (uf, ua), gu = one((-1, 0, 0, 0))
+        # the forward autotuner ranks schedules by the forward alone, while the
+        # adjoint's kernels hold more registers (some spill where the forward's
+        # do not): its choice for reference, then the gradient autotuner's
         autotune(op, init)
         auto = op.schedule()
         (af, aa), ga = one(auto)
-        # the forward autotuner ranks schedules by the forward alone, while the
-        # adjoint's kernels hold more registers (some spill where the forward's
-        # do not), so the register tiles of 32x64 and 32x128 are also timed on
-        # the gradient itself and the fastest is reported
-        best = ((af, aa), ga, auto)
-        for shape in (2, 3):
-            for T_ in range(2, min(4, wave_tiled_max_depth(so, 3, tile=tile_table(3)[shape - 1])) + 1):
-                c = Schedule(T_, so // 2, shape, 0, tile_table(3)[shape - 1], 0)
-                if tuple(c) == tuple(auto):
-                    continue
-                t, g = one(c)
-                if sum(t) < sum(best[0]):
-                    best = (t, g, op.schedule())
-        (tf, ta), gt, tuned = best
+        op.autotune_gradient(40, 2, 8, init.src_xyz, init.rec_xyz, ckpt_every=20)
+        op._scratch = None
+        tuned = op.schedule()
+        (tf, ta), gt = one(tuned)
         T = tuned[0]
         rows.append({"space_order": so, "nt": nt, "schedule": sched_dict(tuned),
                      "forward_autotuned_schedule": sched_dict(auto),

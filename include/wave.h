@@ -302,6 +302,31 @@ wave_status wave_autotune_points(wave_ctx* ctx, int32_t trial_steps, int32_t rep
                                  const double* rec_xyz, void* scratch_dev, size_t scratch_bytes,
                                  double* best_seconds_per_step, int32_t* timed_trials);
 
+/* The autotuner for gradients (wave_adjoint_grad), since the paper's
+ * auto-tuner times the operator as it will run (implementation chapter,
+ * "Auto-tuning") and the adjoint's kernels hold more registers than the
+ * forward's, so the forward's ranking does not carry over: first
+ * wave_autotune_points (exhaustive) with these points, then trial gradients
+ * of trial_steps steps with checkpoints every K (a zero wavelet and a zero
+ * residual) for the forward's winner, the untiled sweep and the register
+ * tiles of depth 2..min(4, max_T) on 32x64 and 32x128 (2D: 1x1024); the
+ * fastest is kept, a time-tiled schedule only when more than 1 % faster than
+ * the untiled sweep.  Synchronises.  *best_seconds_per_step: the kept
+ * schedule's gradient trial per step; *timed_trials (may be NULL): forward
+ * and gradient candidates timed.  Scratch: wave_autotune_gradient_scratch_bytes
+ * (device).  Errors: WAVE_ESTATE (a diffusion context), WAVE_EINVAL,
+ * WAVE_ENOMEM, WAVE_EHIP. */
+wave_status wave_autotune_gradient(wave_ctx* ctx, int32_t trial_steps, int32_t repeats, int32_t max_T,
+                                   int32_t ckpt_every, int32_t nsrc, const double* src_xyz, int32_t nrec,
+                                   const double* rec_xyz, void* scratch_dev, size_t scratch_bytes,
+                                   double* best_seconds_per_step, int32_t* timed_trials);
+
+/* Scratch bytes wave_autotune_gradient needs (the larger of the forward
+ * trials' and a trial gradient's with its outputs and zero inputs); 0 for a
+ * null or diffusion context or invalid arguments.  Host-only. */
+size_t wave_autotune_gradient_scratch_bytes(const wave_ctx* ctx, int32_t trial_steps, int32_t nsrc, int32_t nrec,
+                                            int32_t ckpt_every);
+
 /* Scratch bytes wave_autotune_points needs for these point counts (with
  * nsrc = nrec = 0 also what wave_autotune and wave_autotune_guided need);
  * 0 for a null context or invalid counts.  Host-only. */

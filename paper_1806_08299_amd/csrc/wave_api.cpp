@@ -1867,6 +1867,110 @@ wave_status wave_autotune_points(wave_ctx* c, int32_t trial_steps, int32_t repea
   return s;
 }
 
+// Scratch of wave_autotune_gradient: the forward trials' (autotune_bytes),
+// or a gradient's layout for trial_steps steps with checkpoints every K
+// followed by grad_m [N], grad_q [steps][nsrc], a zero wavelet
+// [steps][nsrc] and a zero residual [steps][nrec], whichever is larger.
+static size_t grad_tune_bytes(const wave_ctx* c, int trial_steps, int nsrc, int nrec, int K) {
+  const size_t g = layout(c, trial_steps, nsrc, nrec, K, 1).total + align_up(sizeof(float) * c->N) +
+                   2 * align_up(sizeof(float) * (size_t)trial_steps * nsrc) +
+                   align_up(sizeof(float) * (size_t)trial_steps * nrec);
+  return std::max(autotune_bytes(c, trial_steps, nsrc, nrec), g);
+}
+
+size_t wave_autotune_gradient_scratch_bytes(const wave_ctx* c, int32_t trial_steps, int32_t nsrc, int32_t nrec,
+                                            int32_t K) {
+  if (!c || c->eq != 0 || trial_steps < 1 || nsrc < 0 || nrec < 0 || K < 1) return 0;
+  return grad_tune_bytes(c, trial_steps, nsrc, nrec, K);
+}
+
+wave_status wave_autotune_gradient(wave_ctx* c, int32_t trial_steps, int32_t repeats, int32_t max_T, int32_t K,
+                                   int32_t nsrc, const double* src_xyz, int32_t nrec, const double* rec_xyz,
+                                   void* scratch, size_t scratch_bytes, double* best, int32_t* timed) {
+  if (!c) return WAVE_EINVAL;
+  if (c->eq != 0) return fail(c, WAVE_ESTATE, "not a wave-equation context");
+  if (trial_steps < 1 || repeats < 1 || K < 1 || nsrc < 0 || nrec < 0)
+    return fail(c, WAVE_EINVAL, "need trial_steps, repeats, K >= 1 and point counts >= 0");
+  wave_status s;
+  if ((s = validate_coords(c, nsrc, src_xyz)) || (s = validate_coords(c, nrec, rec_xyz))) return s;
+  if (!scratch || scratch_bytes < grad_tune_bytes(c, trial_steps, nsrc, nrec, K))
+    return fail(c, WAVE_ENOMEM, "scratch buffer too small");
+  // 1. the forward autotuner with the operator's points
+  int n = 0;
+  double fbest = 0;
+  s = autotune_impl(c, trial_steps, repeats, max_T, 0, nsrc, src_xyz, nrec, rec_xyz, scratch, scratch_bytes, &fbest,
+                    &n);
+  if (s != WAVE_OK) return s;
+  // 2. trial gradients of the forward's winner, the untiled sweep and the
+  //    register tiles of depth 2..4 on 32 x 64 and 32 x 128 (2D: 1 x 1024):
+  //    the adjoint's kernels hold more registers than the forward's, so the
+  //    forward's ranking does not carry over
+  struct GC { int T, skew, shape, slab, zc; };
+  std::vector<GC> cands;
+  cands.push_back({c->T, c->skew, c->shape, c->slab, c->zchunks});
+  cands.push_back({-1, c->R, c->dim == 3 ? 1 : 0, 0, c->T < 0 ? c->zchunks : 0});
+  const int tcap = std::min(4, max_T > 0 ? max_T : 8);
+  for (int sh : (c->dim == 3 ? std::vector<int>{2, 3} : std::vector<int>{0}))
+    for (int T = 2; T <= std::min(tcap, tiled_tmax(c->R, c->dim, sh)); ++T) cands.push_back({T, c->R, sh, 0, 0});
+  const Layout L = layout(c, trial_steps, nsrc, nrec, K, 1);
+  char* base = (char*)scratch + L.total;
+  float* gm = (float*)base;
+  base += align_up(sizeof(float) * c->N);
+  float* gq = (float*)base;
+  base += align_up(sizeof(float) * (size_t)trial_steps * nsrc);
+  float* wav = (float*)base;
+  base += align_up(sizeof(float) * (size_t)trial_steps * nsrc);
+  float* res = (float*)base;
+  if (nsrc > 0 && (s = fill(c, wav, (int64_t)trial_steps * nsrc, 0.0f))) return s;
+  if (nrec > 0 && (s = fill(c, res, (int64_t)trial_steps * nrec, 0.0f))) return s;
+  const GC first = cands[0];
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  auto time_grad = [&](const GC& k) -> double {
+    if (apply_schedule(c, k.T, k.skew, k.shape, k.slab, k.zc) != WAVE_OK) return 1e300;
+    double tmin = 1e300;
+    for (int r = 0; r < repeats + 1; ++r) {
+      hipEventRecord(e0, c->stream);
+      const wave_status st = wave_adjoint_grad(c, trial_steps, nsrc, src_xyz, wav, nrec, rec_xyz, res, gm,
+                                               nsrc > 0 ? gq : nullptr, K, 0, scratch, scratch_bytes);
+      if (st != WAVE_OK) return 1e300;
+      hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) return 1e300;
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) tmin = std::min(tmin, (double)ms * 1e-3);
+    }
+    return tmin;
+  };
+  double bt = 1e300, ut = 1e300;
+  GC bk = first, uk = cands[1];
+  for (size_t i = 0; i < cands.size(); ++i) {
+    bool dup = false;
+    for (size_t j = 0; j < i; ++j)
+      dup |= cands[j].T == cands[i].T && cands[j].shape == cands[i].shape && cands[j].slab == cands[i].slab &&
+             cands[j].zc == cands[i].zc && cands[j].skew == cands[i].skew;
+    if (dup) continue;
+    const double t = time_grad(cands[i]);
+    ++n;
+    if (cands[i].T < 0 && t < ut) { ut = t; uk = cands[i]; }
+    if (t < bt) { bt = t; bk = cands[i]; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->err.clear();
+  // a time-tiled schedule replaces the untiled sweep only beyond the trials'
+  // spread (1 %)
+  if (bk.T >= 1 && ut < 1e300 && bt > 0.99 * ut) { bk = uk; bt = ut; }
+  if (bt >= 1e300) bk = first;
+  s = apply_schedule(c, bk.T, bk.skew, bk.shape, bk.slab, bk.zc);
+  if (s != WAVE_OK) return s;
+  c->ck.valid = false;
+  if (best) *best = bt < 1e300 ? bt / trial_steps : fbest;
+  if (timed) *timed = n;
+  return WAVE_OK;
+}
+
 
 
 // ----------------------------------------------------------- estimators

@@ -167,6 +167,8 @@ def lib():
             "wave_autotune_guided": (i32, [P, i32, i32, i32, i32, P, sz, P, P]),
             "wave_autotune_points": (i32, [P, i32, i32, i32, i32, i32, P, i32, P, P, sz, P, P]),
             "wave_autotune_scratch_bytes": (sz, [P, i32, i32, i32]),
+            "wave_autotune_gradient": (i32, [P, i32, i32, i32, i32, i32, P, i32, P, P, sz, P, P]),
+            "wave_autotune_gradient_scratch_bytes": (sz, [P, i32, i32, i32, i32]),
             "wave_tiled_max_depth": (i32, [i32, i32, i32, i32]),
             "wave_tile_extent": (i32, [i32, i32, P, P]),
             "wave_ai_naive": (dbl, [dbl, i32]),
@@ -335,6 +337,24 @@ def wave_autotune_points(ctx, trial_steps, repeats, max_T, keep, src_xyz, rec_xy
     st = lib().wave_autotune_points(ctx, trial_steps, repeats, max_T, keep, src.shape[0], _hptr(src), rec.shape[0],
                                     _hptr(rec), ctypes.c_void_p(scratch.data_ptr()),
                                     scratch.numel() * scratch.element_size(), ctypes.byref(best), ctypes.byref(n))
+    _check(st, ctx)
+    return best.value, n.value
+
+
+def wave_autotune_gradient_scratch_bytes(ctx, trial_steps, nsrc, nrec, ckpt_every) -> int:
+    return int(lib().wave_autotune_gradient_scratch_bytes(ctx, trial_steps, nsrc, nrec, ckpt_every))
+
+
+def wave_autotune_gradient(ctx, trial_steps, repeats, max_T, ckpt_every, src_xyz, rec_xyz, scratch, ndim=3):
+    """The autotuner for gradients: returns (seconds per step of the kept
+    schedule's trial gradient, number of candidates timed)."""
+    src = _coords(src_xyz, ndim)
+    rec = _coords(rec_xyz, ndim)
+    best = ctypes.c_double()
+    n = ctypes.c_int32()
+    st = lib().wave_autotune_gradient(ctx, trial_steps, repeats, max_T, ckpt_every, src.shape[0], _hptr(src),
+                                      rec.shape[0], _hptr(rec), ctypes.c_void_p(scratch.data_ptr()),
+                                      scratch.numel() * scratch.element_size(), ctypes.byref(best), ctypes.byref(n))
     _check(st, ctx)
     return best.value, n.value
 
@@ -512,6 +532,18 @@ class WaveOp:
         nrec = 0 if rec_xyz is None else len(rec_xyz)
         sc = self.scratch(wave_autotune_scratch_bytes(self.ctx, trial_steps, nsrc, nrec))
         best, _ = wave_autotune_points(self.ctx, trial_steps, repeats, max_T, keep, src_xyz, rec_xyz, sc, self.ndim)
+        return best
+
+    def autotune_gradient(self, trial_steps=40, repeats=2, max_T=0, src_xyz=None, rec_xyz=None, ckpt_every=20):
+        """Tune the schedule for adjoint_grad (wave_autotune_gradient): the
+        forward autotuner, then trial gradients of its winner, the untiled
+        sweep and a few register tiles; returns the kept schedule's trial
+        seconds per step."""
+        nsrc = 0 if src_xyz is None else len(src_xyz)
+        nrec = 0 if rec_xyz is None else len(rec_xyz)
+        sc = self.scratch(wave_autotune_gradient_scratch_bytes(self.ctx, trial_steps, nsrc, nrec, ckpt_every))
+        best, _ = wave_autotune_gradient(self.ctx, trial_steps, repeats, max_T, ckpt_every, src_xyz, rec_xyz, sc,
+                                         self.ndim)
         return best
 
     def forward(self, nt, src_xyz=None, wavelet=None, rec_xyz=None, u_init=None, want_final=False,

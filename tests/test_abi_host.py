@@ -201,3 +201,5 @@ def test_null_context_entry_points(W):
     assert L.wave_autotune(None, 10, 1, 0, None, 0, None) == -1
     assert L.wave_autotune_guided(None, 10, 1, 0, 4, None, 0, None, None) == -1
     assert L.wave_autotune_points(None, 10, 1, 0, 0, 0, None, 0, None, None, 0, None, None) == -1
+    assert L.wave_autotune_gradient_scratch_bytes(None, 10, 0, 0, 5) == 0
+    assert L.wave_autotune_gradient(None, 10, 1, 0, 5, 0, None, 0, None, None, 0, None, None) == -1

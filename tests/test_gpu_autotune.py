@@ -101,3 +101,37 @@ def test_autotune_with_points(keep):
     with pytest.raises(WaveError) as e:
         wave_autotune_points(d.ctx, 4, 1, 2, keep, [[1.0, 1.0, 1.0]], None, dsc)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("shape", [(40, 60, 140), (60, 1100)])
+def test_autotune_gradient(shape):
+    """wave_autotune_gradient keeps a schedule whose gradient is bitwise that
+    of the untiled sweep; its scratch covers the forward trials and a trial
+    gradient; too little scratch and a diffusion context are refused."""
+    from paper_1806_08299_amd import DiffOp, WaveError
+    from paper_1806_08299_amd.wave import (wave_autotune_gradient, wave_autotune_gradient_scratch_bytes,
+                                           wave_autotune_scratch_bytes)
+    from test_gpu_adjoint import _grad, _op as _aop, _problem
+    P = _problem(so=4, shape=shape, nbl=4, nt=16, seed=7, nsrc=2, nrec=9)
+    P["resid"] = np.random.default_rng(8).standard_normal((P["nt"], P["rec"].shape[0])).astype(np.float32)
+    op = _aop(P, P["m0"], time_tile=-1)
+    gm_u, gq_u = _grad(op, P, 6)
+    nb = wave_autotune_gradient_scratch_bytes(op.ctx, 12, len(P["src"]), len(P["rec"]), 6)
+    assert nb >= wave_autotune_scratch_bytes(op.ctx, 12, len(P["src"]), len(P["rec"]))
+    sc = op.scratch(nb)
+    best, timed = wave_autotune_gradient(op.ctx, 12, 1, 4, 6, P["src"], P["rec"], sc, len(shape))
+    print("shape %s: kept %s, %.3g s per step, %d timed" % (shape, op.schedule(), best, timed), flush=True)
+    assert best > 0 and timed >= 3
+    gm_t, gq_t = _grad(op, P, 6)
+    assert np.array_equal(gm_t, gm_u) and np.array_equal(gq_t, gq_u), op.schedule()
+    assert op.autotune_gradient(8, 1, 2, P["src"], P["rec"], ckpt_every=4) > 0
+    gm_t, gq_t = _grad(op, P, 6)
+    assert np.array_equal(gm_t, gm_u) and np.array_equal(gq_t, gq_u), op.schedule()
+    with pytest.raises(WaveError) as e:
+        wave_autotune_gradient(op.ctx, 12, 1, 4, 6, P["src"], P["rec"], sc[:nb - 1], len(shape))
+    assert e.value.status == -4
+    d = DiffOp((40, 30, 70), (1.0, 1.0, 1.0), 0.01, 1.0, 4)
+    assert wave_autotune_gradient_scratch_bytes(d.ctx, 4, 0, 0, 2) == 0
+    with pytest.raises(WaveError) as e:
+        wave_autotune_gradient(d.ctx, 4, 1, 2, 2, None, None, torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == -6
