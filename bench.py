@@ -311,14 +311,15 @@ def gradient_bench(args, dev, stream):
     out = {"workload": "%s, model %s, nt=%d, checkpoints every %d"
                        % (init.name, "x".join(map(str, init.shape)), init.nt, K), "unit": "Gpts/s"}
 
-    def one(sched):
+    def one(sched, keep=0):
         op.set_schedule(*sched)
         best = None
         for _ in range(2):
             e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
             torch.cuda.synchronize()
             e0.record(stream)
-            rec, _ = op.forward(init.nt, init.src_xyz, wv, init.rec_xyz, ckpt_every=K, adjoint_scratch=True)
+            rec, _ = op.forward(init.nt, init.src_xyz, wv, init.rec_xyz, ckpt_every=K, adjoint_scratch=True,
+                                keep_segments=keep)
             resid = rec - dobs
             e1.record(stream)
             gm, _ = op.adjoint_grad(init.nt, init.src_xyz, wv, init.rec_xyz, resid, K, reuse=True)
@@ -353,6 +354,7 @@ def gradient_bench(args, dev, stream):
                        "bytes": "forward %.0f + checkpoint copies; recompute %.0f + adjoint %.0f B per point-update"
                                 % (b_f, b_h, b_a)}
     log("gradient %s: fwd %.3f s + recompute/adjoint %.3f s" % (tuned, tf, ta))
+    out["kept_history"] = kept_history_leg(op, init, K, one, tuned, gm, (tf, ta), (b_f, b_h, b_a))
     if not args.no_untiled:
         (uf, ua), _ = one((-1, 0, 0, tuned[3] if tuned[0] < 0 else 0))
         out["untiled"] = {"value": round(init.npts * init.nt / (uf + ua) / 1e9, 2),
@@ -364,6 +366,39 @@ def gradient_bench(args, dev, stream):
     if not args.no_untiled:
         out["by_order"] = gradient_orders(init, dev, stream, 200 if args.quick else 400, K)
     return out
+
+
+def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
+    """The same gradient with the history of as many last checkpoint segments
+    as the free HBM holds kept from the forward (wave_forward with scratch
+    beyond the adjoint's layout): those segments skip their recompute, whose
+    20 B per point-update become 4 B in the forward."""
+    import torch
+    from paper_1806_08299_amd.wave import wave_history_segment_bytes, wave_last_kept_segments, wave_scratch_bytes
+    op._scratch = None
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    seg = wave_history_segment_bytes(op.ctx, K)
+    base = wave_scratch_bytes(op.ctx, init.nt, len(init.src_xyz), len(init.rec_xyz), K, 1)
+    nseg = -(-init.nt // K)
+    keep = int(max(0, min(nseg, (free - base - (6 << 30)) // seg)))
+    (kf, ka), gm = one(sched, keep)
+    kept = wave_last_kept_segments(op.ctx)
+    same = bool(torch.equal(gm, gm_ref))
+    op._scratch = None
+    torch.cuda.empty_cache()
+    b_f, b_h, b_a = bpp
+    ks = max(0, init.nt - (nseg - kept) * K)                       # steps in kept segments
+    fwd_bytes = (b_f * (init.nt - ks) + b_h * ks + 8.0 * (nseg - kept)) * init.npts
+    adj_bytes = (b_h * (init.nt - ks) + b_a * init.nt + 16.0 * (nseg - kept)) * init.npts
+    log("gradient, history of %d of %d segments kept: fwd %.3f s + recompute/adjoint %.3f s" % (kept, nseg, kf, ka))
+    return {"segments_kept": kept, "segments": nseg, "scratch_GB": round((base + keep * seg) / 1e9, 1),
+            "value": round(init.npts * init.nt / (kf + ka) / 1e9, 2),
+            "forward_with_checkpoints_s": round(kf, 4), "recompute_plus_adjoint_s": round(ka, 4),
+            "speedup_vs_full_recompute": round(sum(t_ref) / (kf + ka), 3),
+            "bitwise_equal_to_full_recompute": same,
+            "forward_achieved_GBs": round(fwd_bytes / kf / 1e9, 1),
+            "recompute_adjoint_achieved_GBs": round(adj_bytes / ka / 1e9, 1)}
 
 
 def gradient_orders(init, dev, stream, nt, K):

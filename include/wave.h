@@ -194,12 +194,29 @@ wave_status wave_forward(wave_ctx* ctx, int32_t nt,
  *                   changed either; 0: run that forward here.
  * Forward segments are recomputed from checkpoints with the time-tiled
  * kernel (storing their history), then swept backwards with the time-tiled
- * adjoint kernel that accumulates the imaging condition. */
+ * adjoint kernel that accumulates the imaging condition.
+ *   scratch_dev / scratch_bytes  at least wave_scratch_bytes(ctx, nt, nsrc,
+ *                   nrec, K, 1).  With reuse = 0, every further
+ *                   wave_history_segment_bytes(ctx, K) keeps one more segment's
+ *                   history (the last segments first) straight from the
+ *                   forward, which then skips that segment's checkpoint and
+ *                   the adjoint its recompute: the recompute's 20 B per
+ *                   point-update become 4 B in the forward.  The gradient is
+ *                   bitwise the same for any number of kept segments. */
 wave_status wave_adjoint_grad(wave_ctx* ctx, int32_t nt,
                               int32_t nsrc, const double* src_xyz, const float* wavelet_dev,
                               int32_t nrec, const double* rec_xyz, const float* resid_dev,
                               float* grad_m_dev, float* grad_wavelet_dev,
                               int32_t ckpt_every, int32_t reuse, void* scratch_dev, size_t scratch_bytes);
+
+/* Host-only.  Bytes of one kept segment's history in wave_adjoint_grad's
+ * scratch (K levels of N floats, aligned); 0 for a NULL or diffusion context
+ * or K < 1. */
+size_t wave_history_segment_bytes(const wave_ctx* ctx, int32_t ckpt_every);
+
+/* Host-only.  Segments whose history the last wave_adjoint_grad on this
+ * context kept from its forward (0 before any); -1 for a NULL context. */
+int32_t wave_last_kept_segments(const wave_ctx* ctx);
 
 /* Many independent shots advanced together, for example the sources of one
  * survey (the paper leaves multi-operator batching to future work; this is

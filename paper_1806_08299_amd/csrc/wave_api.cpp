@@ -71,6 +71,7 @@ struct wave_ctx {
   struct {
     bool valid = false;
     int nt = 0, K = 0, nsrc = 0, nrec = 0;
+    int kept = 0;                // last segments whose history the forward kept
     const void* scratch = nullptr;
     const float* wavelet = nullptr;
     std::vector<double> src, rec;
@@ -80,6 +81,7 @@ struct wave_ctx {
   Recorder* rec = nullptr;       // non-null: device operations are recorded, not launched
   uint64_t id = 0;               // unique per context of the process
   uint64_t gen = 0;              // bumped by every call that rewrites the caller's scratch
+  int last_kept = 0;             // segments the last wave_adjoint_grad kept the history of
   void* static_scratch = nullptr;   // device address of this GPU's static scratch array (wave_forward_static)
   BatchGraph* graph = nullptr;   // last batch led by this context
   hipStream_t cap = nullptr;     // stream the batch is captured on (the caller's may be the null stream)
@@ -705,10 +707,13 @@ wave_status validate_coords(wave_ctx* c, int n, const double* xyz) {
   return WAVE_OK;
 }
 
-// Forward core shared by wave_forward and the adjoint's own forward.
+// Forward core shared by wave_forward and the adjoint's own forward.  With
+// keep_hist, the checkpoint segments from keep_from on store every level they
+// produce (segment j's K levels at keep_hist + (j - keep_from) K N, level
+// n + 1 of step n at slot n - jK) instead of a checkpoint.
 wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const float* wav, int nrec,
                          const double* rec, float* rec_out, const float* u_init, float* u_final, int K,
-                         char* scratch, const Layout& L) {
+                         char* scratch, const Layout& L, float* keep_hist = nullptr, int keep_from = 0) {
   PointTable PS, PR;
   build_points(c, nsrc, src, PS);
   build_points(c, rec_out ? nrec : 0, rec, PR);
@@ -747,15 +752,22 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
   SweepAux* auxd = (SweepAux*)(scratch + L.aux);
   if ((s = upload_aux(c, &DS, table, PR.npts > 0 ? &DR : nullptr, samp, auxd, c->aux_host[0]))) return s;
   Window win{&DS, table, PR.npts > 0 ? &DR : nullptr, samp, nullptr, 0, nullptr, auxd};
+  if (keep_hist && !ck) return fail(c, WAVE_EINVAL, "kept history needs checkpoints");
   int n = 0;
   while (n < nt) {
-    if (ck && n % K == 0) {
-      const int seg = n / K;
+    const int seg = ck ? n / K : 0;
+    const bool kept = keep_hist && seg >= keep_from;
+    if (ck && n % K == 0 && !kept) {
       if ((s = copy(c, W.C(), ck + (size_t)seg * 2 * c->N, c->N))) return s;
       if ((s = copy(c, W.P(), ck + (size_t)seg * 2 * c->N + c->N, c->N))) return s;
     }
     const int upto = ck ? std::min(nt, (n / K + 1) * K) : nt;
-    if ((s = run_steps(c, W, n, upto - n, 1, win))) return s;
+    Window w = win;
+    if (kept) {
+      w.hist = keep_hist + (size_t)(seg - keep_from) * K * c->N;
+      w.hist_base = seg * K + 1;
+    }
+    if ((s = run_steps(c, W, n, upto - n, 1, w))) return s;
     n = upto;
   }
   if (rec_out && nrec > 0) {
@@ -1100,6 +1112,15 @@ void wave_destroy(wave_ctx* c) {
   delete c;
 }
 
+// Segments (the last ones) whose history fits into scratch beyond the
+// adjoint's layout.
+static int kept_segments(const wave_ctx* c, int nt, int nsrc, int nrec, int K, size_t scratch_bytes) {
+  const Layout L = layout(c, nt, nsrc, nrec, K, 1);
+  if (K < 1 || L.nseg < 1 || scratch_bytes <= L.total) return 0;
+  const size_t seg_bytes = align_up(sizeof(float) * (size_t)K * c->N);
+  return (int)std::min<size_t>((size_t)L.nseg, (scratch_bytes - L.total) / seg_bytes);
+}
+
 size_t wave_scratch_bytes(const wave_ctx* c, int32_t nt, int32_t nsrc, int32_t nrec, int32_t K, int32_t adjoint) {
   if (!c || nt < 0 || nsrc < 0 || nrec < 0 || K < 0) return 0;
   if (c->eq != 0) return 2 * align_up(sizeof(float) * c->N);   // diffusion: wave_autotune's two levels
@@ -1120,9 +1141,19 @@ wave_status wave_forward(wave_ctx* c, int32_t nt, int32_t nsrc, const double* sr
   const Layout L = layout(c, nt, nsrc, nrec, K, 0);
   if (!scratch || scratch_bytes < L.total) return fail(c, WAVE_ENOMEM, "scratch buffer too small");
   c->gen++;
-  s = forward_core(c, nt, nsrc, src, wav, nrec, rec, rec_out, u_init, u_final, K, (char*)scratch, L);
+  // scratch beyond the adjoint's layout (of which this one is a prefix) keeps
+  // the history of the last whole segments that fit for the adjoint
+  float* keep_hist = nullptr;
+  int nkeep = 0;
+  if (K > 0 && !u_init) {
+    nkeep = kept_segments(c, nt, nsrc, nrec, K, scratch_bytes);
+    if (nkeep > 0) keep_hist = (float*)((char*)scratch + layout(c, nt, nsrc, nrec, K, 1).total);
+  }
+  s = forward_core(c, nt, nsrc, src, wav, nrec, rec, rec_out, u_init, u_final, K, (char*)scratch, L, keep_hist,
+                   L.nseg - nkeep);
   if (s != WAVE_OK) return s;
   if (K > 0 && !u_init) {
+    c->ck.kept = nkeep;
     c->ck.valid = true;
     c->ck.nt = nt;
     c->ck.K = K;
@@ -1139,10 +1170,11 @@ wave_status wave_forward(wave_ctx* c, int32_t nt, int32_t nsrc, const double* sr
 // checkpoints of a forward with interval K in the scratch of layout L.  Point
 // tables are rebuilt into the same scratch regions: for the same coordinates
 // their bytes equal those of the forward (so a recorded forward still reads
-// what it wrote).
+// what it wrote).  Segments from keep_from on read the history the forward
+// kept in keep_hist and are not recomputed.
 static wave_status adjoint_core(wave_ctx* c, int nt, int nsrc, const double* src, const float* wav, int nrec,
                                 const double* rec, const float* resid, float* grad_m, float* grad_q, int K, char* sc,
-                                const Layout& L) {
+                                const Layout& L, float* keep_hist = nullptr, int keep_from = 0) {
   wave_status s;
   PointTable PS, PR;
   build_points(c, nsrc, src, PS);
@@ -1197,12 +1229,17 @@ static wave_status adjoint_core(wave_ctx* c, int nt, int nsrc, const double* src
   Window bw{bw_inj, atab, bw_smp, asmp, hist, 0, grad_m, auxd + 2};
   for (int seg = L.nseg - 1; seg >= 0; --seg) {
     const int c0 = seg * K, c1 = std::min(nt, c0 + K);
-    U.cur = 0;
-    U.prev = 1;
-    if ((s = copy(c, ck + (size_t)seg * 2 * c->N, U.C(), c->N))) return s;
-    if ((s = copy(c, ck + (size_t)seg * 2 * c->N + c->N, U.P(), c->N))) return s;
-    fw.hist_base = c0 + 1;
-    if ((s = run_steps(c, U, c0, c1 - c0, 1, fw))) return s;
+    if (keep_hist && seg >= keep_from) {
+      bw.hist = keep_hist + (size_t)(seg - keep_from) * K * c->N;
+    } else {
+      U.cur = 0;
+      U.prev = 1;
+      if ((s = copy(c, ck + (size_t)seg * 2 * c->N, U.C(), c->N))) return s;
+      if ((s = copy(c, ck + (size_t)seg * 2 * c->N + c->N, U.P(), c->N))) return s;
+      fw.hist_base = c0 + 1;
+      if ((s = run_steps(c, U, c0, c1 - c0, 1, fw))) return s;
+      bw.hist = hist;
+    }
     bw.hist_base = c0 + 1;
     if ((s = run_steps(c, M, c1 - 1, c1 - c0, -1, bw))) return s;
   }
@@ -1246,13 +1283,29 @@ wave_status wave_adjoint_grad(wave_ctx* c, int32_t nt, int32_t nsrc, const doubl
     if (!ok) return fail(c, WAVE_ESTATE, "no matching checkpoints from a preceding forward");
   }
   c->gen++;
+  // scratch beyond the layout keeps the history of the last whole segments
+  // that fit, straight from the forward: those are not recomputed (with
+  // reuse, the segments the preceding wave_forward kept)
+  const int nkeep = reuse ? c->ck.kept : kept_segments(c, nt, nsrc, nrec, K, scratch_bytes);
+  if (reuse && nkeep > kept_segments(c, nt, nsrc, nrec, K, scratch_bytes))
+    return fail(c, WAVE_ESTATE, "scratch smaller than the preceding forward's");
+  float* keep_hist = nkeep > 0 ? (float*)(sc + L.total) : nullptr;
+  const int keep_from = L.nseg - nkeep;
+  c->last_kept = nkeep;
   if (!reuse) {
-    s = forward_core(c, nt, nsrc, src, wav, 0, nullptr, nullptr, nullptr, nullptr, K, sc, L);
+    s = forward_core(c, nt, nsrc, src, wav, 0, nullptr, nullptr, nullptr, nullptr, K, sc, L, keep_hist, keep_from);
     if (s != WAVE_OK) return s;
   }
   c->ck.valid = false;
-  return adjoint_core(c, nt, nsrc, src, wav, nrec, rec, resid, grad_m, grad_q, K, sc, L);
+  return adjoint_core(c, nt, nsrc, src, wav, nrec, rec, resid, grad_m, grad_q, K, sc, L, keep_hist, keep_from);
 }
+
+size_t wave_history_segment_bytes(const wave_ctx* c, int32_t K) {
+  if (!c || c->eq != 0 || K < 1) return 0;
+  return align_up(sizeof(float) * (size_t)K * c->N);
+}
+
+int32_t wave_last_kept_segments(const wave_ctx* c) { return c ? c->last_kept : -1; }
 
 // Replays the recorded operations of every shot on `st` in one interleaved
 // sequence: each shot's non-sweep operations run in its own order; the
@@ -1933,7 +1986,7 @@ wave_status wave_autotune_gradient(wave_ctx* c, int32_t trial_steps, int32_t rep
     for (int r = 0; r < repeats + 1; ++r) {
       hipEventRecord(e0, c->stream);
       const wave_status st = wave_adjoint_grad(c, trial_steps, nsrc, src_xyz, wav, nrec, rec_xyz, res, gm,
-                                               nsrc > 0 ? gq : nullptr, K, 0, scratch, scratch_bytes);
+                                               nsrc > 0 ? gq : nullptr, K, 0, scratch, L.total);
       if (st != WAVE_OK) return 1e300;
       hipEventRecord(e1, c->stream);
       if (hipEventSynchronize(e1) != hipSuccess) return 1e300;

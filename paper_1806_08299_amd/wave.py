@@ -159,6 +159,8 @@ def lib():
             "wave_set_schedule": (i32, [P, i32, i32, P, i32, i32]),
             "wave_get_schedule": (i32, [P, P, P, P, P, P]),
             "wave_scratch_bytes": (sz, [P, i32, i32, i32, i32, i32]),
+            "wave_history_segment_bytes": (sz, [P, i32]),
+            "wave_last_kept_segments": (i32, [P]),
             "wave_forward": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, P, sz]),
             "wave_forward_static": (i32, [P, i32, i32, P, P, i32, P, P, P, P]),
             "wave_adjoint_grad": (i32, [P, i32, i32, P, P, i32, P, P, P, P, i32, i32, P, sz]),
@@ -291,6 +293,14 @@ def wave_forward_static(ctx, nt, src_xyz, wavelet, rec_xyz, rec_out, u_init, u_f
 
 
 WAVE_STATIC_SCRATCH_BYTES = 32 << 20
+
+
+def wave_history_segment_bytes(ctx, ckpt_every: int) -> int:
+    return int(lib().wave_history_segment_bytes(ctx, ckpt_every))
+
+
+def wave_last_kept_segments(ctx) -> int:
+    return int(lib().wave_last_kept_segments(ctx))
 
 
 def wave_adjoint_grad(ctx, nt, src_xyz, wavelet, rec_xyz, resid, grad_m, grad_wavelet, ckpt_every, reuse,
@@ -547,7 +557,10 @@ class WaveOp:
         return best
 
     def forward(self, nt, src_xyz=None, wavelet=None, rec_xyz=None, u_init=None, want_final=False,
-                ckpt_every=0, adjoint_scratch=False):
+                ckpt_every=0, adjoint_scratch=False, keep_segments=0):
+        """Forward (wave_forward).  adjoint_scratch sizes the scratch for a
+        following adjoint_grad(reuse=True); keep_segments > 0 (with it) also
+        keeps the history of that many last segments for that adjoint."""
         src = _coords(src_xyz, self.ndim)
         rec = _coords(rec_xyz, self.ndim)
         if wavelet is not None:
@@ -555,17 +568,26 @@ class WaveOp:
         rec_out = torch.empty((nt, rec.shape[0]), dtype=torch.float32, device=self.device) if rec.shape[0] else None
         fin = torch.empty((2,) + self.shape, dtype=torch.float32, device=self.device) if want_final else None
         nb = wave_scratch_bytes(self.ctx, nt, src.shape[0], rec.shape[0], ckpt_every, 1 if adjoint_scratch else 0)
+        if adjoint_scratch and keep_segments > 0 and ckpt_every > 0:
+            nb += keep_segments * wave_history_segment_bytes(self.ctx, ckpt_every)
         sc = self.scratch(nb)
         wave_forward(self.ctx, nt, src, wavelet, rec, rec_out, u_init, fin, ckpt_every, sc, self.ndim)
         return rec_out, fin
 
-    def adjoint_grad(self, nt, src_xyz, wavelet, rec_xyz, resid, ckpt_every, want_grad_wavelet=True, reuse=False):
+    def adjoint_grad(self, nt, src_xyz, wavelet, rec_xyz, resid, ckpt_every, want_grad_wavelet=True, reuse=False,
+                     keep_segments=0):
+        """Gradient (wave_adjoint_grad).  keep_segments > 0 sizes the scratch so
+        that the forward keeps the history of that many last segments, which
+        the adjoint then does not recompute (scratch already larger keeps as
+        many as fit); the gradient is bitwise the same."""
         src = _coords(src_xyz, self.ndim)
         rec = _coords(rec_xyz, self.ndim)
         gm = torch.empty(self.shape, dtype=torch.float32, device=self.device)
         gq = torch.empty((nt, src.shape[0]), dtype=torch.float32, device=self.device) \
             if (want_grad_wavelet and src.shape[0]) else None
         nb = wave_scratch_bytes(self.ctx, nt, src.shape[0], rec.shape[0], ckpt_every, 1)
+        if keep_segments > 0 and not reuse:
+            nb += keep_segments * wave_history_segment_bytes(self.ctx, ckpt_every)
         if reuse and (self._scratch is None or self._scratch.numel() < nb):
             reuse = False
         sc = self.scratch(nb)

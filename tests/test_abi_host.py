@@ -203,3 +203,5 @@ def test_null_context_entry_points(W):
     assert L.wave_autotune_points(None, 10, 1, 0, 0, 0, None, 0, None, None, 0, None, None) == -1
     assert L.wave_autotune_gradient_scratch_bytes(None, 10, 0, 0, 5) == 0
     assert L.wave_autotune_gradient(None, 10, 1, 0, 5, 0, None, 0, None, None, 0, None, None) == -1
+    assert L.wave_history_segment_bytes(None, 5) == 0
+    assert L.wave_last_kept_segments(None) == -1

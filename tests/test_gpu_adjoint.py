@@ -100,6 +100,62 @@ def test_checkpoint_interval_does_not_change_gradient(prob):
     assert np.array_equal(gm, base) and np.array_equal(gq, bq)
 
 
+@pytest.mark.parametrize("sched", [(-1, 0, 0, 0, 0), (2, 0, 2, 0, 0), (3, 0, 2, 0, 0), (4, 0, 0, 0, 16)])
+def test_kept_history_bitwise(prob, sched):
+    """Scratch beyond the minimum keeps the last segments' history from the
+    forward, whose recompute is then skipped: the gradient is bitwise that of
+    the full recompute for any number of kept segments, the short last
+    segment (40 steps in segments of 7) and every segment kept included, also
+    when the history comes from a preceding wave_forward that records the
+    receivers (whose traces stay bitwise those of a plain forward)."""
+    from paper_1806_08299_amd.wave import wave_last_kept_segments
+    T, skew, shape, zc, slab = sched
+    print("kept history, schedule", sched, flush=True)
+    op = _op(prob, prob["m0"], time_tile=-1)
+    op.set_schedule(T, skew, shape, zc, slab=slab)
+    wav = torch.from_numpy(prob["wav"]).cuda()
+    resid = torch.from_numpy(prob["resid"]).cuda()
+    K, nseg = 7, 6
+    base = None
+    for keep in (0, 1, 3, 6, 10):           # ascending: the op's scratch only grows
+        gm, gq = op.adjoint_grad(prob["nt"], prob["src"], wav, prob["rec"], resid, K, keep_segments=keep)
+        torch.cuda.synchronize()
+        assert wave_last_kept_segments(op.ctx) == min(keep, nseg), keep
+        gm, gq = gm.cpu().numpy(), gq.cpu().numpy()
+        if base is None:
+            base = (gm, gq)
+            assert_field(gm, prob["ref"]["grad_m"], TOL_GRAD, "grad_m")
+        else:
+            assert np.array_equal(gm, base[0]), keep
+            assert np.array_equal(gq, base[1]), keep
+    # checkpoints and kept history from a preceding forward that also records
+    # the receivers (the op's scratch now holds all 6 segments' history)
+    rec_ref, _ = op.forward(prob["nt"], prob["src"], wav, prob["rec"])
+    rec_k, _ = op.forward(prob["nt"], prob["src"], wav, prob["rec"], ckpt_every=K, adjoint_scratch=True)
+    assert torch.equal(rec_k, rec_ref)
+    gm, gq = op.adjoint_grad(prob["nt"], prob["src"], wav, prob["rec"], resid, K, reuse=True)
+    torch.cuda.synchronize()
+    assert wave_last_kept_segments(op.ctx) == nseg
+    assert np.array_equal(gm.cpu().numpy(), base[0]) and np.array_equal(gq.cpu().numpy(), base[1])
+
+
+def test_kept_history_2d_bitwise():
+    from paper_1806_08299_amd.wave import wave_last_kept_segments
+    P = _problem(so=4, shape=(300, 260), nbl=8, nt=60, seed=3, nsrc=1, nrec=12)
+    rng = np.random.default_rng(3)
+    resid = torch.from_numpy((1e-3 * rng.standard_normal((P["nt"], 12))).astype(np.float32)).cuda()
+    wav = torch.from_numpy(P["wav"]).cuda()
+    for T in (-1, 4):
+        print("kept history 2D, T", T, flush=True)
+        op = _op(P, P["m0"], time_tile=T)
+        base = op.adjoint_grad(P["nt"], P["src"], wav, P["rec"], resid, 9)
+        base = [t.cpu().numpy() for t in base]
+        gm, gq = op.adjoint_grad(P["nt"], P["src"], wav, P["rec"], resid, 9, keep_segments=4)
+        torch.cuda.synchronize()
+        assert wave_last_kept_segments(op.ctx) == 4
+        assert np.array_equal(gm.cpu().numpy(), base[0]) and np.array_equal(gq.cpu().numpy(), base[1])
+
+
 def test_reuse_without_forward_is_rejected(prob):
     from paper_1806_08299_amd import WaveError
     from paper_1806_08299_amd.wave import wave_adjoint_grad, wave_scratch_bytes
