@@ -419,14 +419,15 @@ def gradient_orders(init, dev, stream, nt, K):
         rec0, _ = op.forward(nt, init.src_xyz, wv, init.rec_xyz)
         resid = rec0.clone()
 
-        def one(sched):
+        def one(sched, keep=0):
             op.set_schedule(*sched)
             best, gm = None, None
             for _ in range(2):
                 e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
                 torch.cuda.synchronize()
                 e0.record(stream)
-                op.forward(nt, init.src_xyz, wv, init.rec_xyz, ckpt_every=K, adjoint_scratch=True)
+                op.forward(nt, init.src_xyz, wv, init.rec_xyz, ckpt_every=K, adjoint_scratch=True,
+                           keep_segments=keep)
                 e1.record(stream)
                 gm, _ = op.adjoint_grad(nt, init.src_xyz, wv, init.rec_xyz, resid, K, reuse=True)
                 e2.record(stream)
@@ -447,6 +448,11 @@ def gradient_orders(init, dev, stream, nt, K):
         op._scratch = None
         tuned = op.schedule()
         (tf, ta), gt = one(tuned)
+        # every segment's history kept from the forward (8 x 50 levels fit)
+        nseg = -(-nt // K)
+        (kf, ka), gk = one(tuned, nseg)
+        (kuf, kua), gku = one((-1, 0, 0, 0), nseg)
+        op._scratch = None
         T = tuned[0]
         rows.append({"space_order": so, "nt": nt, "schedule": sched_dict(tuned),
                      "forward_autotuned_schedule": sched_dict(auto),
@@ -458,9 +464,16 @@ def gradient_orders(init, dev, stream, nt, K):
                      "adjoint_bytes_per_point_update": wave_bytes_per_point(T, 2),
                      "bitwise_equal_to_untiled": bool(torch.equal(gt, gu)),
                      "forward_with_checkpoints_s": round(tf, 4), "recompute_plus_adjoint_s": round(ta, 4),
-                     "untiled_forward_s": round(uf, 4), "untiled_recompute_plus_adjoint_s": round(ua, 4)})
-        log("gradient so%d: %s fwd %.3f + adj %.3f s, untiled %.3f + %.3f s (%.2fx)"
-            % (so, tuned, tf, ta, uf, ua, (uf + ua) / (tf + ta)))
+                     "untiled_forward_s": round(uf, 4), "untiled_recompute_plus_adjoint_s": round(ua, 4),
+                     "kept_history": {"segments_kept": nseg,
+                                      "value": round(init.npts * nt / (kf + ka) / 1e9, 2),
+                                      "untiled_value": round(init.npts * nt / (kuf + kua) / 1e9, 2),
+                                      "speedup_vs_untiled": round((kuf + kua) / (kf + ka), 3),
+                                      "speedup_vs_full_recompute": round((tf + ta) / (kf + ka), 3),
+                                      "bitwise_equal": bool(torch.equal(gk, gt) and torch.equal(gku, gu)),
+                                      "forward_s": round(kf, 4), "adjoint_s": round(ka, 4)}})
+        log("gradient so%d: %s fwd %.3f + adj %.3f s, untiled %.3f + %.3f s (%.2fx); history kept: %.3f + %.3f s, "
+            "untiled %.3f + %.3f s" % (so, tuned, tf, ta, uf, ua, (uf + ua) / (tf + ta), kf, ka, kuf, kua))
         del op
         torch.cuda.empty_cache()
     return rows
