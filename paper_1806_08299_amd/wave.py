@@ -605,18 +605,21 @@ class WaveOp:
 
 
 class WaveFn(torch.autograd.Function):
-    """rec = WaveFn.apply(m, wavelet, op, src_xyz, rec_xyz, ckpt_every).
+    """rec = WaveFn.apply(m, wavelet, op, src_xyz, rec_xyz, ckpt_every, keep_segments).
 
     Forward models the receiver traces [nt, nrec] for squared slowness m and
     source wavelet [nt, nsrc]; backward returns (dL/dm, dL/dwavelet) from the
     time-reversed adjoint sweep with the imaging condition, recomputing the
-    forward in checkpointed segments of ckpt_every steps."""
+    forward in checkpointed segments of ckpt_every steps, except the last
+    keep_segments ones, whose history the forward keeps in the op's scratch
+    (the same gradient, bitwise)."""
 
     @staticmethod
-    def forward(ctx, m, wavelet, op: WaveOp, src_xyz, rec_xyz, ckpt_every: int = 50):
+    def forward(ctx, m, wavelet, op: WaveOp, src_xyz, rec_xyz, ckpt_every: int = 50, keep_segments: int = 0):
         op.set_model(m.detach())
         nt = wavelet.shape[0]
-        rec, _ = op.forward(nt, src_xyz, wavelet.detach(), rec_xyz, ckpt_every=ckpt_every, adjoint_scratch=True)
+        rec, _ = op.forward(nt, src_xyz, wavelet.detach(), rec_xyz, ckpt_every=ckpt_every, adjoint_scratch=True,
+                            keep_segments=keep_segments)
         # The checkpoints left in the op's scratch belong to this forward only
         # while no other forward has run on the op since.
         token = object()
@@ -626,6 +629,7 @@ class WaveFn(torch.autograd.Function):
         ctx.src_xyz = src_xyz
         ctx.rec_xyz = rec_xyz
         ctx.ckpt_every = ckpt_every
+        ctx.keep_segments = keep_segments
         ctx.save_for_backward(m.detach(), wavelet.detach())
         return rec
 
@@ -638,9 +642,10 @@ class WaveFn(torch.autograd.Function):
         if not reuse:                      # another forward ran on the op: its model and checkpoints are not ours
             op.set_model(m)
         gm, gq = op.adjoint_grad(nt, ctx.src_xyz, wavelet, ctx.rec_xyz, grad_rec.contiguous(), ctx.ckpt_every,
-                                 want_grad_wavelet=ctx.needs_input_grad[1], reuse=reuse)
+                                 want_grad_wavelet=ctx.needs_input_grad[1], reuse=reuse,
+                                 keep_segments=ctx.keep_segments)
         op._fwd_token = None               # adjoint_grad overwrote the scratch
-        return gm, gq, None, None, None, None
+        return gm, gq, None, None, None, None, None
 
 
 class DiffOp:

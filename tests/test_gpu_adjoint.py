@@ -208,6 +208,24 @@ def test_autograd_function(prob):
     assert abs(fd - gd) / abs(gd) < 5e-3
 
 
+def test_autograd_kept_history_bitwise(prob):
+    """WaveFn with the history of the last segments kept from its forward
+    gives the gradients of the full recompute, bitwise."""
+    from paper_1806_08299_amd import WaveFn
+    from paper_1806_08299_amd.wave import wave_last_kept_segments
+    dobs = torch.from_numpy(prob["dobs"].astype(np.float32)).cuda()
+    out = []
+    for keep in (0, 3):
+        op = _op(prob, prob["m0"], time_tile=2)
+        m = torch.from_numpy(prob["m0"]).cuda().requires_grad_(True)
+        wav = torch.from_numpy(prob["wav"]).cuda().requires_grad_(True)
+        rec = WaveFn.apply(m, wav, op, prob["src"], prob["rec"], 10, keep)
+        (0.5 * ((rec - dobs) ** 2).sum()).backward()
+        assert wave_last_kept_segments(op.ctx) == keep
+        out.append((m.grad.cpu(), wav.grad.cpu()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
 def test_gradient_2d_every_order():
     for so in (2, 4, 8, 16):
         P = _problem(so=so, shape=(50, 61), nbl=5, nt=30, seed=so, nsrc=1, nrec=6)
