@@ -110,6 +110,16 @@ def test_full_size_gradient_dot_product_and_schedule_independence():
         torch.cuda.synchronize()
         assert torch.equal(gm2, gm), (T, shape, K)
         del gm2
+    # the history of the last 8 of 40 segments kept from the forward (61 GB)
+    print("gradient: 8 segments kept", flush=True)
+    op.set_schedule(-1, 0, 1, 0)
+    gm2, _ = op.adjoint_grad(w.nt, w.src_xyz, q, w.rec_xyz, dd, 50, want_grad_wavelet=False, keep_segments=8)
+    torch.cuda.synchronize()
+    from paper_1806_08299_amd.wave import wave_last_kept_segments
+    assert wave_last_kept_segments(op.ctx) == 8
+    assert torch.equal(gm2, gm)
+    del gm2, op
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("so,scheds", [(2, [(4, 2, 8), (4, 2, 0), (2, 2, 32)]), (8, [(1, 2, 4), (2, 2, 0)])])
