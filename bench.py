@@ -371,8 +371,9 @@ def gradient_bench(args, dev, stream):
 def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
     """The same gradient with the history of as many last checkpoint segments
     as the free HBM holds kept from the forward (wave_forward with scratch
-    beyond the adjoint's layout): those segments skip their recompute, whose
-    20 B per point-update become 4 B in the forward."""
+    beyond the adjoint's layout): those segments skip their recompute (20 B
+    per point-update); the untiled forward writes their levels straight into
+    the history, the time-tiled one stores them beside its own (4 B)."""
     import torch
     from paper_1806_08299_amd.wave import wave_history_segment_bytes, wave_last_kept_segments, wave_scratch_bytes
     op._scratch = None
@@ -389,7 +390,8 @@ def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
     torch.cuda.empty_cache()
     b_f, b_h, b_a = bpp
     ks = max(0, init.nt - (nseg - kept) * K)                       # steps in kept segments
-    fwd_bytes = (b_f * (init.nt - ks) + b_h * ks + 8.0 * (nseg - kept)) * init.npts
+    b_k = b_f if sched[0] < 0 else b_h      # the untiled sweep writes kept levels straight into their slots
+    fwd_bytes = (b_f * (init.nt - ks) + b_k * ks + 8.0 * (nseg - kept)) * init.npts
     adj_bytes = (b_h * (init.nt - ks) + b_a * init.nt + 16.0 * (nseg - kept)) * init.npts
     log("gradient, history of %d of %d segments kept: fwd %.3f s + recompute/adjoint %.3f s" % (kept, nseg, kf, ka))
     return {"segments_kept": kept, "segments": nseg, "scratch_GB": round((base + keep * seg) / 1e9, 1),

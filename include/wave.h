@@ -169,7 +169,10 @@ size_t wave_scratch_bytes(const wave_ctx* ctx, int32_t nt, int32_t nsrc, int32_t
  *   u_final_dev device [2][N] out = (u^{nt}, u^{nt-1}) or NULL
  *   ckpt_every  0: no checkpoints; K > 0: keep checkpoints in scratch so that a
  *               following wave_adjoint_grad(..., reuse = 1) can skip the forward
- *   scratch_dev / scratch_bytes  from wave_scratch_bytes(ctx, nt, nsrc, nrec, K, K > 0)
+ *   scratch_dev / scratch_bytes  from wave_scratch_bytes(ctx, nt, nsrc, nrec, K, K > 0);
+ *               with K > 0 and u_init_dev NULL, every wave_history_segment_bytes(ctx, K)
+ *               beyond wave_scratch_bytes(ctx, nt, nsrc, nrec, K, 1) keeps one more
+ *               segment's history for that adjoint (as in wave_adjoint_grad)
  * Points outside the grid contribute nothing (their corners are dropped). */
 wave_status wave_forward(wave_ctx* ctx, int32_t nt,
                          int32_t nsrc, const double* src_xyz, const float* wavelet_dev,
@@ -200,9 +203,12 @@ wave_status wave_forward(wave_ctx* ctx, int32_t nt,
  *                   wave_history_segment_bytes(ctx, K) keeps one more segment's
  *                   history (the last segments first) straight from the
  *                   forward, which then skips that segment's checkpoint and
- *                   the adjoint its recompute: the recompute's 20 B per
- *                   point-update become 4 B in the forward.  The gradient is
- *                   bitwise the same for any number of kept segments. */
+ *                   the adjoint its recompute (20 B per point-update).  The
+ *                   untiled forward writes those levels straight into their
+ *                   history slots (no extra bytes); the time-tiled and skewed
+ *                   ones store them beside their own levels (4 B per
+ *                   point-update).  The gradient is bitwise the same for any
+ *                   number of kept segments. */
 wave_status wave_adjoint_grad(wave_ctx* ctx, int32_t nt,
                               int32_t nsrc, const double* src_xyz, const float* wavelet_dev,
                               int32_t nrec, const double* rec_xyz, const float* resid_dev,

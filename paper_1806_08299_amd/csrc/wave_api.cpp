@@ -707,6 +707,34 @@ wave_status validate_coords(wave_ctx* c, int n, const double* xyz) {
   return WAVE_OK;
 }
 
+// Untiled steps [step0, step0 + steps) written straight into a contiguous run
+// of history slots: level L > L0 lives at slot L - L0 - 1 of `hist`, levels L0
+// and L0 - 1 stay in W's (cur, prev).  Every step reads its two levels where
+// they lie and writes the new one out of place, so the history costs no store
+// beyond the level itself.
+wave_status run_steps_direct(wave_ctx* c, const Waves& W, int step0, int steps, const Window& win, float* hist,
+                             int L0) {
+  auto level = [&](int L) -> float* {
+    if (L == L0) return W.C();
+    if (L == L0 - 1) return W.P();
+    return hist + (size_t)(L - L0 - 1) * c->N;
+  };
+  Plan p;
+  wave_status s = make_plan(c, KIND_UNTILED, 1, p);
+  if (s != WAVE_OK) return s;
+  for (int n = step0; n < step0 + steps; ++n) {
+    SweepArgs A = window_args(c, win);
+    A.cur = level(n);
+    A.prev = level(n - 1);
+    A.outA = level(n + 1);
+    A.outB = nullptr;
+    A.step0 = n;
+    A.dir = 1;
+    if ((s = launch_window(c, p, A)) != WAVE_OK) return s;
+  }
+  return WAVE_OK;
+}
+
 // Forward core shared by wave_forward and the adjoint's own forward.  With
 // keep_hist, the checkpoint segments from keep_from on store every level they
 // produce (segment j's K levels at keep_hist + (j - keep_from) K N, level
@@ -753,6 +781,10 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
   if ((s = upload_aux(c, &DS, table, PR.npts > 0 ? &DR : nullptr, samp, auxd, c->aux_host[0]))) return s;
   Window win{&DS, table, PR.npts > 0 ? &DR : nullptr, samp, nullptr, 0, nullptr, auxd};
   if (keep_hist && !ck) return fail(c, WAVE_EINVAL, "kept history needs checkpoints");
+  // the untiled sweep writes the kept levels straight into their slots
+  const bool direct = keep_hist && c->T < 0;
+  const int L0 = keep_from * K;
+  bool ran_direct = false;
   int n = 0;
   while (n < nt) {
     const int seg = ck ? n / K : 0;
@@ -762,13 +794,25 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
       if ((s = copy(c, W.P(), ck + (size_t)seg * 2 * c->N + c->N, c->N))) return s;
     }
     const int upto = ck ? std::min(nt, (n / K + 1) * K) : nt;
-    Window w = win;
-    if (kept) {
-      w.hist = keep_hist + (size_t)(seg - keep_from) * K * c->N;
-      w.hist_base = seg * K + 1;
+    if (kept && direct) {
+      if ((s = run_steps_direct(c, W, n, upto - n, win, keep_hist, L0))) return s;
+      ran_direct = true;
+    } else {
+      Window w = win;
+      if (kept) {
+        w.hist = keep_hist + (size_t)(seg - keep_from) * K * c->N;
+        w.hist_base = seg * K + 1;
+      }
+      if ((s = run_steps(c, W, n, upto - n, 1, w))) return s;
     }
-    if ((s = run_steps(c, W, n, upto - n, 1, w))) return s;
     n = upto;
+  }
+  // where the last two levels lie
+  const float* fin_c = W.C();
+  const float* fin_p = W.P();
+  if (ran_direct) {
+    fin_c = nt > L0 ? keep_hist + (size_t)(nt - L0 - 1) * c->N : W.C();
+    fin_p = nt - 1 > L0 ? keep_hist + (size_t)(nt - L0 - 2) * c->N : (nt - 1 == L0 ? W.C() : W.P());
   }
   if (rec_out && nrec > 0) {
     if (PR.npts > 0) {
@@ -784,8 +828,8 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
     }
   }
   if (u_final) {
-    if ((s = copy(c, W.C(), u_final, c->N))) return s;
-    if ((s = copy(c, W.P(), u_final + c->N, c->N))) return s;
+    if ((s = copy(c, fin_c, u_final, c->N))) return s;
+    if ((s = copy(c, fin_p, u_final + c->N, c->N))) return s;
   }
   return WAVE_OK;
 }

@@ -107,7 +107,9 @@ def test_kept_history_bitwise(prob, sched):
     the full recompute for any number of kept segments, the short last
     segment (40 steps in segments of 7) and every segment kept included, also
     when the history comes from a preceding wave_forward that records the
-    receivers (whose traces stay bitwise those of a plain forward)."""
+    receivers (whose traces and final state stay bitwise those of a plain
+    forward; the untiled sweep writes kept levels straight into their
+    history slots)."""
     from paper_1806_08299_amd.wave import wave_last_kept_segments
     T, skew, shape, zc, slab = sched
     print("kept history, schedule", sched, flush=True)
@@ -130,9 +132,10 @@ def test_kept_history_bitwise(prob, sched):
             assert np.array_equal(gq, base[1]), keep
     # checkpoints and kept history from a preceding forward that also records
     # the receivers (the op's scratch now holds all 6 segments' history)
-    rec_ref, _ = op.forward(prob["nt"], prob["src"], wav, prob["rec"])
-    rec_k, _ = op.forward(prob["nt"], prob["src"], wav, prob["rec"], ckpt_every=K, adjoint_scratch=True)
-    assert torch.equal(rec_k, rec_ref)
+    rec_ref, fin_ref = op.forward(prob["nt"], prob["src"], wav, prob["rec"], want_final=True)
+    rec_k, fin_k = op.forward(prob["nt"], prob["src"], wav, prob["rec"], want_final=True, ckpt_every=K,
+                              adjoint_scratch=True)
+    assert torch.equal(rec_k, rec_ref) and torch.equal(fin_k, fin_ref)
     gm, gq = op.adjoint_grad(prob["nt"], prob["src"], wav, prob["rec"], resid, K, reuse=True)
     torch.cuda.synchronize()
     assert wave_last_kept_segments(op.ctx) == nseg
