@@ -336,14 +336,19 @@ def gradient_bench(args, dev, stream):
                 "forward_with_checkpoints_s": round(tf, 4), "recompute_plus_adjoint_s": round(ta, 4),
                 "grad_finite": bool(torch.isfinite(gm).all().item())})
     # Roofline of the two phases: algorithmic bytes of their sweeps (forward
-    # 16 B or 20/T B per point-update; recompute storing the history + 4 B;
-    # adjoint with imaging + 4 + 8/T B) over the phase's HIP-event time; the
+    # 16 B or 20/T B per point-update; recompute storing the history + 4 B,
+    # none for the untiled one; adjoint with imaging + 4 + 8/T B) over the
+    # phase's HIP-event time; the
     # per-kernel split is in profiles/gradient_kernels_const2000_256cube_so8.txt.
     T = tuned[0]
     b_f, b_h, b_a = (wave_bytes_per_point(T, md) for md in (0, 1, 2))
+    if T < 0:      # the untiled recompute starts from the checkpoint and writes its levels into the history
+        b_h, restore = b_f, 0.0
+    else:
+        restore = 8.0 * 2                                            # restoring the two checkpoint levels
     nseg = -(-init.nt // K)
     fwd_bytes = (b_f * init.nt + 8.0 * nseg) * init.npts            # + checkpoint copies (read + write a level)
-    adj_bytes = ((b_h + b_a) * init.nt + 8.0 * 2 * nseg) * init.npts  # + restoring the checkpoints
+    adj_bytes = ((b_h + b_a) * init.nt + restore * nseg) * init.npts
     out["adjoint_bytes_per_point_update"] = b_a
     out["history_bytes_per_point_update"] = b_h
     out["roofline"] = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
@@ -391,8 +396,9 @@ def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
     b_f, b_h, b_a = bpp
     ks = max(0, init.nt - (nseg - kept) * K)                       # steps in kept segments
     b_k = b_f if sched[0] < 0 else b_h      # the untiled sweep writes kept levels straight into their slots
+    restore = 0.0 if sched[0] < 0 else 16.0  # the untiled recompute reads its checkpoint in place
     fwd_bytes = (b_f * (init.nt - ks) + b_k * ks + 8.0 * (nseg - kept)) * init.npts
-    adj_bytes = (b_h * (init.nt - ks) + b_a * init.nt + 16.0 * (nseg - kept)) * init.npts
+    adj_bytes = (b_h * (init.nt - ks) + b_a * init.nt + restore * (nseg - kept)) * init.npts
     log("gradient, history of %d of %d segments kept: fwd %.3f s + recompute/adjoint %.3f s" % (kept, nseg, kf, ka))
     return {"segments_kept": kept, "segments": nseg, "scratch_GB": round((base + keep * seg) / 1e9, 1),
             "value": round(init.npts * init.nt / (kf + ka) / 1e9, 2),

@@ -1275,6 +1275,17 @@ static wave_status adjoint_core(wave_ctx* c, int nt, int nsrc, const double* src
     const int c0 = seg * K, c1 = std::min(nt, c0 + K);
     if (keep_hist && seg >= keep_from) {
       bw.hist = keep_hist + (size_t)(seg - keep_from) * K * c->N;
+    } else if (c->T < 0) {
+      // untiled: the recompute reads its first two levels from the checkpoint
+      // and writes every level straight into its history slot
+      Waves Ck;
+      Ck.buf[0] = ck + (size_t)seg * 2 * c->N;
+      Ck.buf[1] = Ck.buf[0] + c->N;
+      Ck.buf[2] = Ck.buf[3] = nullptr;
+      Window fwd = fw;
+      fwd.hist = nullptr;
+      if ((s = run_steps_direct(c, Ck, c0, c1 - c0, fwd, hist, c0))) return s;
+      bw.hist = hist;
     } else {
       U.cur = 0;
       U.prev = 1;
