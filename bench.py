@@ -586,11 +586,14 @@ def batch_bench(args, dev, stream):
     log("batch: batched forward %.3f s (first call %.3f s), gradient %.3f s (first call %.3f s)"
         % (t_fwd, t_first, tg, tg_first))
     # algorithmic bytes: forward 16 B per point-update (20/T with a time
-    # tile); gradient: forward with checkpoints + recompute with history +
-    # adjoint with imaging, per shot with its own schedule
+    # tile); gradient: forward with checkpoints + recompute with history (the
+    # untiled one writes its levels straight into the history: the forward's
+    # bytes) + adjoint with imaging, per shot with its own schedule
+    def grad_bpp(T):
+        return (wave_bytes_per_point(T, 0) + wave_bytes_per_point(T, 0 if T < 0 else 1)
+                + wave_bytes_per_point(T, 2))
     fb = sum(wave_bytes_per_point(op.schedule().T, 0) * w.npts for op, w in zip(ops, S)) * nt
-    gb = sum(sum(wave_bytes_per_point(op.schedule().T, md) for md in (0, 1, 2)) * w.npts
-             for op, w in zip(ops, S)) * nt
+    gb = sum(grad_bpp(op.schedule().T) * w.npts for op, w in zip(ops, S)) * nt
     roof = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
             "forward_achieved": round(fb / t_fwd / 1e9, 1), "forward_frac": round(fb / t_fwd / 1e9 / HBM_PEAK_GBS, 4),
             "gradient_achieved": round(gb / tg / 1e9, 1), "gradient_frac": round(gb / tg / 1e9 / HBM_PEAK_GBS, 4)}
