@@ -707,11 +707,14 @@ wave_status validate_coords(wave_ctx* c, int n, const double* xyz) {
   return WAVE_OK;
 }
 
-// Untiled steps [step0, step0 + steps) written straight into a contiguous run
-// of history slots: level L > L0 lives at slot L - L0 - 1 of `hist`, levels L0
-// and L0 - 1 stay in W's (cur, prev).  Every step reads its two levels where
-// they lie and writes the new one out of place, so the history costs no store
-// beyond the level itself.
+// Steps [step0, step0 + steps) of the untiled sweep or the register tiles
+// written straight into a contiguous run of history slots: level L > L0 lives
+// at slot L - L0 - 1 of `hist`, levels L0 and L0 - 1 stay in W's (cur, prev).
+// Every window reads its two levels where they lie and writes its last two
+// into their own slots, out of place; a deeper window stores the levels in
+// between as history (its last two land on the slots its outputs name, with
+// the same values), so the history costs no store beyond the levels
+// themselves.
 wave_status run_steps_direct(wave_ctx* c, const Waves& W, int step0, int steps, const Window& win, float* hist,
                              int L0) {
   auto level = [&](int L) -> float* {
@@ -719,18 +722,27 @@ wave_status run_steps_direct(wave_ctx* c, const Waves& W, int step0, int steps, 
     if (L == L0 - 1) return W.P();
     return hist + (size_t)(L - L0 - 1) * c->N;
   };
-  Plan p;
-  wave_status s = make_plan(c, KIND_UNTILED, 1, p);
-  if (s != WAVE_OK) return s;
-  for (int n = step0; n < step0 + steps; ++n) {
+  const bool untiled = c->T < 0;
+  int done = 0;
+  while (done < steps) {
+    const int T = untiled ? 1 : std::min(c->T, steps - done);
+    Plan p;
+    wave_status s = make_plan(c, untiled ? KIND_UNTILED : KIND_TILED, T, p);
+    if (s != WAVE_OK) return s;
+    const int n = step0 + done;
     SweepArgs A = window_args(c, win);
     A.cur = level(n);
     A.prev = level(n - 1);
-    A.outA = level(n + 1);
-    A.outB = nullptr;
+    A.outA = level(n + T);
+    A.outB = T >= 2 ? level(n + T - 1) : nullptr;
+    if (T >= 2) {
+      A.hist = hist;
+      A.hist_base = L0 + 1;
+    }
     A.step0 = n;
     A.dir = 1;
     if ((s = launch_window(c, p, A)) != WAVE_OK) return s;
+    done += T;
   }
   return WAVE_OK;
 }
@@ -781,8 +793,9 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
   if ((s = upload_aux(c, &DS, table, PR.npts > 0 ? &DR : nullptr, samp, auxd, c->aux_host[0]))) return s;
   Window win{&DS, table, PR.npts > 0 ? &DR : nullptr, samp, nullptr, 0, nullptr, auxd};
   if (keep_hist && !ck) return fail(c, WAVE_EINVAL, "kept history needs checkpoints");
-  // the untiled sweep writes the kept levels straight into their slots
-  const bool direct = keep_hist && c->T < 0;
+  // the untiled sweep and the register tiles write the kept levels straight
+  // into their slots (the skewed schedule stores them beside its own)
+  const bool direct = keep_hist && (c->T < 0 || c->slab == 0);
   const int L0 = keep_from * K;
   bool ran_direct = false;
   int n = 0;
@@ -1275,9 +1288,9 @@ static wave_status adjoint_core(wave_ctx* c, int nt, int nsrc, const double* src
     const int c0 = seg * K, c1 = std::min(nt, c0 + K);
     if (keep_hist && seg >= keep_from) {
       bw.hist = keep_hist + (size_t)(seg - keep_from) * K * c->N;
-    } else if (c->T < 0) {
-      // untiled: the recompute reads its first two levels from the checkpoint
-      // and writes every level straight into its history slot
+    } else if (c->T < 0 || c->slab == 0) {
+      // untiled or register tiles: the recompute reads its first two levels
+      // from the checkpoint and writes every level straight into its slot
       Waves Ck;
       Ck.buf[0] = ck + (size_t)seg * 2 * c->N;
       Ck.buf[1] = Ck.buf[0] + c->N;
