@@ -336,16 +336,14 @@ def gradient_bench(args, dev, stream):
                 "forward_with_checkpoints_s": round(tf, 4), "recompute_plus_adjoint_s": round(ta, 4),
                 "grad_finite": bool(torch.isfinite(gm).all().item())})
     # Roofline of the two phases: algorithmic bytes of their sweeps (forward
-    # 16 B or 20/T B per point-update; recompute storing the history + 4 B,
-    # none for the untiled one; adjoint with imaging + 4 + 8/T B) over the
-    # phase's HIP-event time; the
+    # 16 B or 20/T B per point-update; recompute storing the history,
+    # recompute_bpp; adjoint with imaging + 4 + 8/T B) over the phase's
+    # HIP-event time; the
     # per-kernel split is in profiles/gradient_kernels_const2000_256cube_so8.txt.
     T = tuned[0]
-    b_f, b_h, b_a = (wave_bytes_per_point(T, md) for md in (0, 1, 2))
-    if T < 0:      # the untiled recompute starts from the checkpoint and writes its levels into the history
-        b_h, restore = b_f, 0.0
-    else:
-        restore = 8.0 * 2                                            # restoring the two checkpoint levels
+    b_f, b_a = wave_bytes_per_point(T, 0), wave_bytes_per_point(T, 2)
+    b_h = recompute_bpp(tuned)
+    restore = 8.0 * 2 if tuned[5] > 0 else 0.0   # only the skewed recompute restores its checkpoint levels
     nseg = -(-init.nt // K)
     fwd_bytes = (b_f * init.nt + 8.0 * nseg) * init.npts            # + checkpoint copies (read + write a level)
     adj_bytes = ((b_h + b_a) * init.nt + restore * nseg) * init.npts
@@ -373,6 +371,19 @@ def gradient_bench(args, dev, stream):
     return out
 
 
+def recompute_bpp(sched):
+    """Algorithmic bytes per point-update of a step that stores the history:
+    the untiled sweep and the register tiles run out of place straight into
+    the history slots (read u^n, u^{n-1}, b once per window, write every level
+    once: 12/T + 4 B, 16 untiled); the skewed schedule stores the history
+    beside its in-place level (the library's history-mode figure)."""
+    from paper_1806_08299_amd.wave import wave_bytes_per_point
+    T, slab = sched[0], sched[5]
+    if T < 1:
+        return 16.0
+    return 12.0 / T + 4.0 if slab == 0 else wave_bytes_per_point(T, 1)
+
+
 def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
     """The same gradient with the history of as many last checkpoint segments
     as the free HBM holds kept from the forward (wave_forward with scratch
@@ -395,8 +406,8 @@ def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
     torch.cuda.empty_cache()
     b_f, b_h, b_a = bpp
     ks = max(0, init.nt - (nseg - kept) * K)                       # steps in kept segments
-    b_k = b_f if sched[0] < 0 else b_h      # the untiled sweep writes kept levels straight into their slots
-    restore = 0.0 if sched[0] < 0 else 16.0  # the untiled recompute reads its checkpoint in place
+    b_k = b_h                                       # kept forward steps store the history as the recompute does
+    restore = 16.0 if sched[5] > 0 else 0.0         # only the skewed recompute restores its checkpoint levels
     fwd_bytes = (b_f * (init.nt - ks) + b_k * ks + 8.0 * (nseg - kept)) * init.npts
     adj_bytes = (b_h * (init.nt - ks) + b_a * init.nt + restore * (nseg - kept)) * init.npts
     log("gradient, history of %d of %d segments kept: fwd %.3f s + recompute/adjoint %.3f s" % (kept, nseg, kf, ka))
@@ -586,14 +597,12 @@ def batch_bench(args, dev, stream):
     log("batch: batched forward %.3f s (first call %.3f s), gradient %.3f s (first call %.3f s)"
         % (t_fwd, t_first, tg, tg_first))
     # algorithmic bytes: forward 16 B per point-update (20/T with a time
-    # tile); gradient: forward with checkpoints + recompute with history (the
-    # untiled one writes its levels straight into the history: the forward's
-    # bytes) + adjoint with imaging, per shot with its own schedule
-    def grad_bpp(T):
-        return (wave_bytes_per_point(T, 0) + wave_bytes_per_point(T, 0 if T < 0 else 1)
-                + wave_bytes_per_point(T, 2))
+    # tile); gradient: forward with checkpoints + recompute with history
+    # (recompute_bpp) + adjoint with imaging, per shot with its own schedule
+    def grad_bpp(sc):
+        return wave_bytes_per_point(sc[0], 0) + recompute_bpp(sc) + wave_bytes_per_point(sc[0], 2)
     fb = sum(wave_bytes_per_point(op.schedule().T, 0) * w.npts for op, w in zip(ops, S)) * nt
-    gb = sum(grad_bpp(op.schedule().T) * w.npts for op, w in zip(ops, S)) * nt
+    gb = sum(grad_bpp(op.schedule()) * w.npts for op, w in zip(ops, S)) * nt
     roof = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
             "forward_achieved": round(fb / t_fwd / 1e9, 1), "forward_frac": round(fb / t_fwd / 1e9 / HBM_PEAK_GBS, 4),
             "gradient_achieved": round(gb / tg / 1e9, 1), "gradient_frac": round(gb / tg / 1e9 / HBM_PEAK_GBS, 4)}
@@ -606,7 +615,8 @@ def batch_bench(args, dev, stream):
                                     "gradient_branch_per_radius": round(npts * nt / tg1 / 1e9, 2),
                                     "bitwise_equal_to_sequential": same1,
                                     "note": "the default is a graph branch per radius for the forward, one branch for "
-                                            "the gradient; here the other layout (WAVE_BATCH_BRANCHES=0, then =1)"},
+                                            "the gradient; here the other layout (WAVE_BATCH_BRANCHES=0, then =1), "
+                                            "timed after the default (later gradient calls of a process run faster)"},
             "forward": {"value": round(npts * nt / t_fwd / 1e9, 2), "s": round(t_fwd, 4),
                         "first_call_s": round(t_first, 4), "sequential_value": round(npts * nt / t_seq / 1e9, 2),
                         "speedup_vs_sequential": round(t_seq / t_fwd, 3), "bitwise_equal_to_sequential": same_fwd},
