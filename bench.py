@@ -399,7 +399,17 @@ def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
     base = wave_scratch_bytes(op.ctx, init.nt, len(init.src_xyz), len(init.rec_xyz), K, 1)
     nseg = -(-init.nt // K)
     keep = int(max(0, min(nseg, (free - base - (6 << 30)) // seg)))
-    (kf, ka), gm = one(sched, keep)
+    while True:
+        try:
+            (kf, ka), gm = one(sched, keep)
+            break
+        except torch.cuda.OutOfMemoryError:    # the free figure was optimistic: ask for half
+            op._scratch = None
+            torch.cuda.empty_cache()
+            keep //= 2
+            log("kept history: out of memory, retrying with %d segments" % keep)
+            if keep == 0:
+                return {"skipped": "no scratch for kept history"}
     kept = wave_last_kept_segments(op.ctx)
     same = bool(torch.equal(gm, gm_ref))
     op._scratch = None
