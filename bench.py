@@ -343,7 +343,7 @@ def gradient_bench(args, dev, stream):
     T = tuned[0]
     b_f, b_a = wave_bytes_per_point(T, 0), wave_bytes_per_point(T, 2)
     b_h = recompute_bpp(tuned)
-    restore = 8.0 * 2 if tuned[5] > 0 else 0.0   # only the skewed recompute restores its checkpoint levels
+    restore = 0.0                                 # the recompute reads its checkpoint in place
     nseg = -(-init.nt // K)
     fwd_bytes = (b_f * init.nt + 8.0 * nseg) * init.npts            # + checkpoint copies (read + write a level)
     adj_bytes = ((b_h + b_a) * init.nt + restore * nseg) * init.npts
@@ -373,15 +373,12 @@ def gradient_bench(args, dev, stream):
 
 def recompute_bpp(sched):
     """Algorithmic bytes per point-update of a step that stores the history:
-    the untiled sweep and the register tiles run out of place straight into
-    the history slots (read u^n, u^{n-1}, b once per window, write every level
-    once: 12/T + 4 B, 16 untiled); the skewed schedule stores the history
-    beside its in-place level (the library's history-mode figure)."""
-    from paper_1806_08299_amd.wave import wave_bytes_per_point
+    every schedule runs out of place straight into the history slots, reading
+    u^n, u^{n-1} and b once per launch and writing every level once: 12/T + 4 B
+    for a register tile of depth T, 16 for a single-step launch (the untiled
+    sweep and the skewed schedule's slab steps)."""
     T, slab = sched[0], sched[5]
-    if T < 1:
-        return 16.0
-    return 12.0 / T + 4.0 if slab == 0 else wave_bytes_per_point(T, 1)
+    return 16.0 if (T < 1 or slab > 0) else 12.0 / T + 4.0
 
 
 def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
@@ -417,7 +414,7 @@ def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
     b_f, b_h, b_a = bpp
     ks = max(0, init.nt - (nseg - kept) * K)                       # steps in kept segments
     b_k = b_h                                       # kept forward steps store the history as the recompute does
-    restore = 16.0 if sched[5] > 0 else 0.0         # only the skewed recompute restores its checkpoint levels
+    restore = 0.0                                   # the recompute reads its checkpoint in place
     fwd_bytes = (b_f * (init.nt - ks) + b_k * ks + 8.0 * (nseg - kept)) * init.npts
     adj_bytes = (b_h * (init.nt - ks) + b_a * init.nt + restore * (nseg - kept)) * init.npts
     log("gradient, history of %d of %d segments kept: fwd %.3f s + recompute/adjoint %.3f s" % (kept, nseg, kf, ka))

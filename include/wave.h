@@ -203,12 +203,12 @@ wave_status wave_forward(wave_ctx* ctx, int32_t nt,
  *                   wave_history_segment_bytes(ctx, K) keeps one more segment's
  *                   history (the last segments first) straight from the
  *                   forward, which then skips that segment's checkpoint and
- *                   the adjoint its recompute (20 B per point-update).  The
- *                   untiled forward writes those levels straight into their
- *                   history slots (no extra bytes); the time-tiled and skewed
- *                   ones store them beside their own levels (4 B per
- *                   point-update).  The gradient is bitwise the same for any
- *                   number of kept segments. */
+ *                   the adjoint its recompute.  Every schedule writes those
+ *                   levels (and the recomputed ones) out of place straight into
+ *                   their history slots, so keeping them costs the forward no
+ *                   extra bytes beyond a deep register tile's intermediate
+ *                   levels.  The gradient is bitwise the same for any number
+ *                   of kept segments. */
 wave_status wave_adjoint_grad(wave_ctx* ctx, int32_t nt,
                               int32_t nsrc, const double* src_xyz, const float* wavelet_dev,
                               int32_t nrec, const double* rec_xyz, const float* resid_dev,

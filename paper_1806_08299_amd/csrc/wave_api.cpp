@@ -583,8 +583,18 @@ SweepArgs window_args(const wave_ctx* c, const Window& win) {
 // is read at the point only, which the in-place update reads before writing.
 // Slab j's steps touch about Z + T s + 2r planes, which stay in the
 // last-level cache between its launches.
-wave_status run_steps_skewed(wave_ctx* c, Waves& W, int step0, int steps, int dir, const Window& win) {
+// With `slots` (forward only), every level gets its own slot instead: level
+// L > L0 at slot L - L0 - 1, levels L0 and L0 - 1 in W's (cur, prev), each
+// step written out of place.  Nothing is overwritten then, and every plane a
+// step reads comes from earlier slab-steps by the same argument.
+wave_status run_steps_skewed(wave_ctx* c, Waves& W, int step0, int steps, int dir, const Window& win,
+                             float* slots = nullptr, int L0 = 0) {
   const int64_t s = c->skew, Z = c->slab;
+  auto level = [&](int L) -> float* {
+    if (L == L0) return W.C();
+    if (L == L0 - 1) return W.P();
+    return slots + (size_t)(L - L0 - 1) * c->N;
+  };
   int done = 0;
   while (done < steps) {
     const int Tw = std::min(c->T, steps - done);
@@ -598,19 +608,26 @@ wave_status run_steps_skewed(wave_ctx* c, Waves& W, int step0, int steps, int di
         wave_status st = make_plan(c, KIND_UNTILED, 1, p, lo, hi);
         if (st != WAVE_OK) return st;
         SweepArgs A = window_args(c, win);
-        // level done+k sits in C() for even k, in P() for odd k
-        float* cur = (k & 1) ? W.P() : W.C();
-        float* old = (k & 1) ? W.C() : W.P();
-        A.cur = cur;
-        A.prev = old;
-        A.outA = old;   // in place over the oldest level
+        if (slots) {
+          const int n = step0 + done + k;
+          A.cur = level(n);
+          A.prev = level(n - 1);
+          A.outA = level(n + 1);
+        } else {
+          // level done+k sits in C() for even k, in P() for odd k
+          float* cur = (k & 1) ? W.P() : W.C();
+          float* old = (k & 1) ? W.C() : W.P();
+          A.cur = cur;
+          A.prev = old;
+          A.outA = old;   // in place over the oldest level
+        }
         A.outB = nullptr;
         A.step0 = step0 + dir * (done + k);
         A.dir = dir;
         if ((st = launch_window(c, p, A)) != WAVE_OK) return st;
       }
     }
-    if (Tw & 1) std::swap(W.cur, W.prev);
+    if ((Tw & 1) && !slots) std::swap(W.cur, W.prev);
     done += Tw;
   }
   return WAVE_OK;
@@ -717,6 +734,10 @@ wave_status validate_coords(wave_ctx* c, int n, const double* xyz) {
 // themselves.
 wave_status run_steps_direct(wave_ctx* c, const Waves& W, int step0, int steps, const Window& win, float* hist,
                              int L0) {
+  if (c->T >= 1 && c->slab > 0) {
+    Waves V = W;
+    return run_steps_skewed(c, V, step0, steps, 1, win, hist, L0);
+  }
   auto level = [&](int L) -> float* {
     if (L == L0) return W.C();
     if (L == L0 - 1) return W.P();
@@ -793,9 +814,8 @@ wave_status forward_core(wave_ctx* c, int nt, int nsrc, const double* src, const
   if ((s = upload_aux(c, &DS, table, PR.npts > 0 ? &DR : nullptr, samp, auxd, c->aux_host[0]))) return s;
   Window win{&DS, table, PR.npts > 0 ? &DR : nullptr, samp, nullptr, 0, nullptr, auxd};
   if (keep_hist && !ck) return fail(c, WAVE_EINVAL, "kept history needs checkpoints");
-  // the untiled sweep and the register tiles write the kept levels straight
-  // into their slots (the skewed schedule stores them beside its own)
-  const bool direct = keep_hist && (c->T < 0 || c->slab == 0);
+  // every schedule writes the kept levels straight into their slots
+  const bool direct = keep_hist != nullptr;
   const int L0 = keep_from * K;
   bool ran_direct = false;
   int n = 0;
@@ -1269,11 +1289,8 @@ static wave_status adjoint_core(wave_ctx* c, int nt, int nsrc, const double* src
   float* ck = (float*)(sc + L.ckpt);
   float* hist = (float*)(sc + L.hist);
   float* aw = (float*)(sc + L.adj_w);
-  Waves U, M;
-  for (int i = 0; i < 4; ++i) {
-    U.buf[i] = c->w[i];
-    M.buf[i] = aw + (size_t)i * c->N;
-  }
+  Waves M;
+  for (int i = 0; i < 4; ++i) M.buf[i] = aw + (size_t)i * c->N;
   if ((s = fill(c, M.C(), c->N, 0.0f))) return s;
   if ((s = fill(c, M.P(), c->N, 0.0f))) return s;
   if ((s = fill(c, grad_m, c->N, 0.0f))) return s;
@@ -1282,30 +1299,20 @@ static wave_status adjoint_core(wave_ctx* c, int nt, int nsrc, const double* src
   const DevPoints* bw_smp = (grad_q && PS.npts > 0) ? &DS : nullptr;
   if ((s = upload_aux(c, &DS, table, nullptr, nullptr, auxd + 1, c->aux_host[1]))) return s;
   if ((s = upload_aux(c, bw_inj, atab, bw_smp, asmp, auxd + 2, c->aux_host[2]))) return s;
-  Window fw{&DS, table, nullptr, nullptr, hist, 0, nullptr, auxd + 1};
+  Window fw{&DS, table, nullptr, nullptr, nullptr, 0, nullptr, auxd + 1};   // history slots come per window
   Window bw{bw_inj, atab, bw_smp, asmp, hist, 0, grad_m, auxd + 2};
   for (int seg = L.nseg - 1; seg >= 0; --seg) {
     const int c0 = seg * K, c1 = std::min(nt, c0 + K);
     if (keep_hist && seg >= keep_from) {
       bw.hist = keep_hist + (size_t)(seg - keep_from) * K * c->N;
-    } else if (c->T < 0 || c->slab == 0) {
-      // untiled or register tiles: the recompute reads its first two levels
-      // from the checkpoint and writes every level straight into its slot
+    } else {
+      // the recompute reads its first two levels from the checkpoint and
+      // writes every level straight into its history slot
       Waves Ck;
       Ck.buf[0] = ck + (size_t)seg * 2 * c->N;
       Ck.buf[1] = Ck.buf[0] + c->N;
       Ck.buf[2] = Ck.buf[3] = nullptr;
-      Window fwd = fw;
-      fwd.hist = nullptr;
-      if ((s = run_steps_direct(c, Ck, c0, c1 - c0, fwd, hist, c0))) return s;
-      bw.hist = hist;
-    } else {
-      U.cur = 0;
-      U.prev = 1;
-      if ((s = copy(c, ck + (size_t)seg * 2 * c->N, U.C(), c->N))) return s;
-      if ((s = copy(c, ck + (size_t)seg * 2 * c->N + c->N, U.P(), c->N))) return s;
-      fw.hist_base = c0 + 1;
-      if ((s = run_steps(c, U, c0, c1 - c0, 1, fw))) return s;
+      if ((s = run_steps_direct(c, Ck, c0, c1 - c0, fw, hist, c0))) return s;
       bw.hist = hist;
     }
     bw.hist_base = c0 + 1;
