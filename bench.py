@@ -384,9 +384,9 @@ def recompute_bpp(sched):
 def kept_history_leg(op, init, K, one, sched, gm_ref, t_ref, bpp):
     """The same gradient with the history of as many last checkpoint segments
     as the free HBM holds kept from the forward (wave_forward with scratch
-    beyond the adjoint's layout): those segments skip their recompute (20 B
-    per point-update); the untiled forward writes their levels straight into
-    the history, the time-tiled one stores them beside its own (4 B)."""
+    beyond the adjoint's layout): those segments skip their recompute
+    (recompute_bpp), and the forward writes their levels straight into the
+    history slots."""
     import torch
     from paper_1806_08299_amd.wave import wave_history_segment_bytes, wave_last_kept_segments, wave_scratch_bytes
     op._scratch = None
